@@ -1,0 +1,131 @@
+"""Benchmark: Ryser subset-steps/s of the dense FP64 permanent on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+Workload: the dense real 32 x 32 matrix with i.i.d. U[0,1) entries (seed
+16578), resident in HBM before timing.  One step is one complete
+perm_dense_f64 call -- staging kernel, the Gray-walk sweep over all 2^31
+column subsets, and the fixed-order reduction -- so one step processes
+2^31 subset-steps.  Prints one JSON line.
+
+roofline: the sweep is bound by the FP64 vector ALU.  Algorithmic work per
+subset-step is 2n + 2 flops (n additions, n multiplications, the sign and
+the accumulation; the count the paper uses for its error estimate).  None of
+it is multiply-add shaped, so one FP64 lane-operation per flop: the ceiling
+is 256 CUs x 64 FP64 lanes/clock x 2.4 GHz = 39.32 Tflop/s (the published
+78.6 TFLOP/s counts an FMA as two flops).  The duration is the average HIP
+event time of one call on the launch stream, which includes the two tiny
+kernels around the sweep (under 0.5 % of it).
+
+cpu_baseline: the CPU oracle (long double, all host threads) timed on a
+bounded sample of the same matrix's Gray walk, scaled to subset-steps/s.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+N = 32
+PEAK_ALU_TFLOPS = 256 * 64 * 2.4e9 / 1e12      # 39.32: one add or mul per lane per clock
+PEAK_FMA_TFLOPS = 78.6                           # published FP64 vector peak (FMA = 2 flops)
+
+
+def cpu_baseline(a, target_seconds=12.0):
+    from oracle.oracle import default
+    orc = default()
+    threads = os.cpu_count() or 1
+    chunk = orc.CHUNK_STEPS
+    nch = 256
+    t0 = time.perf_counter()
+    orc.ryser_sample(a, 0, nch, threads)
+    dt = time.perf_counter() - t0
+    # grow the sample to about target_seconds of wall time
+    nch = int(min(max(nch * target_seconds / max(dt, 1e-3), nch), (1 << (N - 1)) // chunk))
+    t0 = time.perf_counter()
+    orc.ryser_sample(a, 1024, nch, threads)
+    dt = time.perf_counter() - t0
+    steps = nch * chunk
+    return {"value": steps / dt, "unit": "subset-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{steps} of the 2^31 Gray steps of the same 32x32 U[0,1) matrix "
+                      f"({nch} chunks of {chunk} steps, long double), {dt:.2f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on exactly one GPU (no multi-GPU path); use --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2502_16577_amd import api, workloads
+
+    dev = torch.device("cuda:0")
+    a = workloads.uniform(N, workloads.SEED_U32)
+    A = torch.from_numpy(a).to(dev)
+    out = torch.empty((), dtype=torch.float64, device=dev)
+    ws = torch.empty(api.workspace_bytes(1, N), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream(dev)
+
+    for _ in range(args.warmup):
+        api.perm_dense_f64(A, out=out, ws=ws)
+    torch.cuda.synchronize()
+
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for s, e in evs:
+        s.record(stream)
+        api.perm_dense_f64(A, out=out, ws=ws)
+        e.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = [s.elapsed_time(e) for s, e in evs]
+    avg_ms = sum(ev_ms) / len(ev_ms)
+
+    steps_per_call = 2 ** (N - 1)
+    value = steps_per_call * args.steps / wall
+    flops_per_call = (2 * N + 2) * steps_per_call
+    achieved = flops_per_call / (avg_ms * 1e-3) / 1e12
+
+    rec = {
+        "metric": "Ryser subset-steps/s & % FP64 peak; batched perm+grad/s vs plain at 1e-10",
+        "value": value,
+        "unit": "subset-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "dense real 32x32, entries U[0,1) (seed 16578), "
+                               "one perm_dense_f64 call = 2^31 subset-steps",
+                   "n": N, "subset_steps_per_step": steps_per_call},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_ALU_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_ALU_TFLOPS, "traffic": None,
+                     "kernel": "sweep_dense_f64<32>", "event_ms_per_launch": avg_ms,
+                     "flops_per_subset_step": 2 * N + 2,
+                     "frac_of_published_fp64_peak_78.6": achieved / PEAK_FMA_TFLOPS},
+        "result": float(out.item()),
+    }
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(a)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,138 @@
+/*
+ * perm.h -- C ABI of libperm_mi355x.so: matrix permanents on AMD MI355X
+ * (gfx950) by the Gray-code-ordered Ryser / Nijenhuis-Wilf sweep.
+ *
+ * Method (arXiv 2502.16577, Section 2, Algorithm 1): with row sums r_i and the
+ * start vector x_i = a_{i,n-1} - r_i / 2, the 2^(n-1) subsets S of the first
+ * n-1 columns are visited in binary-reflected Gray-code order; step g flips
+ * column j = ctz(g), updates x += s * A[:, j] (s = +1 when the column enters
+ * S, -1 when it leaves), and accumulates (-1)^g * prod_i x_i.  The permanent
+ * is 2 (-1)^(n-1) times that sum.  The iteration space is split into
+ * power-of-two chunks, one per GPU lane, each seeded in closed form from its
+ * Gray code (Algorithm 3 with the chunking of Section 3.2).
+ *
+ * General conventions (all entry points):
+ *   - Dense matrices are DEVICE pointers, row-major: entry (i, j) is at
+ *     A[i * lda + j], lda >= n.  Complex entries are perm_c128 (re, im).
+ *   - Sparse patterns (CSC: col_ptr[n+1], row_idx[nnz], vals[nnz]) are HOST
+ *     pointers: the library validates them and derives the launch plan from
+ *     them before any GPU work, then stages them into the workspace.
+ *   - ws is a DEVICE workspace of at least perm_workspace_bytes(kind, n, m)
+ *     bytes, owned by the caller; the library never allocates device memory
+ *     and keeps no pointer after a call returns.
+ *   - stream is a hipStream_t passed as void* (NULL = the null stream).  All
+ *     calls are asynchronous on that stream except perm_binary_exact, which
+ *     synchronises it to finish the Chinese remaindering on the host.
+ *   - Results are deterministic for fixed inputs and sizes: partial sums are
+ *     combined in a fixed order and no result goes through atomics.
+ *   - n == 0 yields 1 (the empty product); n < 0 or n > PERM_MAX_N is
+ *     PERM_EINVAL.  Errors are reported as negative return values before any
+ *     GPU work is queued, except PERM_EHIP which reports a HIP runtime error.
+ *   - No C++ exceptions cross the ABI.
+ */
+#ifndef PERM_MI355X_H
+#define PERM_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PERM_MAX_N 63
+
+typedef struct {
+    double re, im;
+} perm_c128;
+
+/* Status codes. */
+#define PERM_OK            0
+#define PERM_EINVAL       -1  /* bad argument: n out of range, NULL, lda < n, malformed CSC */
+#define PERM_ERANGE       -2  /* result would not fit (binary: bound above the CRT modulus) */
+#define PERM_EWORKSPACE   -3  /* ws NULL or ws_bytes below perm_workspace_bytes() */
+#define PERM_EHIP         -4  /* a HIP runtime call failed */
+#define PERM_EUNSUPPORTED -5  /* valid request this build does not implement */
+
+/* Workspace kinds for perm_workspace_bytes(). */
+#define PERM_KIND_DENSE_F64   1
+#define PERM_KIND_DENSE_C128  2
+#define PERM_KIND_SPARSE_F64  3
+#define PERM_KIND_BINARY      4
+#define PERM_KIND_GRAD_F64    5
+#define PERM_KIND_GRAD_C128   6
+#define PERM_KIND_BATCHED     7
+
+/* Human-readable text of a status code (static storage). */
+const char *perm_strerror(int status);
+
+/* Library version as 10000*major + 100*minor + patch. */
+int perm_version(void);
+
+/*
+ * Bytes of device workspace a call needs.  kind is one of PERM_KIND_*; n is
+ * the matrix order (for PERM_KIND_BATCHED: the largest order in the batch);
+ * m is nnz for the sparse kinds, the number of matrices for the batched kind,
+ * and ignored otherwise.  Returns 0 for an invalid request.
+ */
+size_t perm_workspace_bytes(int kind, int n, int64_t m);
+
+/*
+ * Permanent of a dense real n x n matrix (Algorithm 1 over 2^(n-1) subsets,
+ * Section 2; chunked as in Algorithm 3).  All arithmetic is FP64; each lane
+ * keeps its x in registers, re-derives it exactly from the Gray code at fixed
+ * intervals, and accumulates its terms with two-sum compensation; lane, block
+ * and grid partials are combined as double-double in a fixed order.
+ *   A    device, row-major, lda >= n
+ *   out  device, one double
+ */
+int perm_dense_f64(int n, const double *A, int64_t lda, double *out,
+                   void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Permanent of a dense complex n x n matrix: the same sweep with complex x
+ * and complex products (Section 1 lists complex matrices among the supported
+ * inputs).
+ *   A    device, row-major perm_c128, lda >= n
+ *   out  device, one perm_c128
+ */
+int perm_dense_c128(int n, const perm_c128 *A, int64_t lda, perm_c128 *out,
+                    void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Permanent of a sparse real n x n matrix in CSC (Algorithm 2, SpaRyser): a
+ * Gray step updates only the rows of column j that hold nonzeros; the product
+ * still runs over all n rows.
+ *   col_ptr  host int32[n+1], col_ptr[0] = 0, nondecreasing, col_ptr[n] = nnz
+ *   row_idx  host int32[nnz], strictly increasing within a column, in [0, n)
+ *   vals     host double[nnz]
+ *   out      device, one double
+ */
+int perm_sparse_f64(int n, const int32_t *col_ptr, const int32_t *row_idx,
+                    const double *vals, int32_t nnz, double *out,
+                    void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Exact permanent of a 0/1 matrix given by its nonzero pattern in CSC (the
+ * number of perfect matchings of its bipartite graph, Section 1).  The sweep
+ * runs on y = 2x, which is integral, modulo n_primes primes just below 2^61;
+ * the residues are combined by Chinese remaindering on the host.
+ *   col_ptr, row_idx  host CSC pattern as for perm_sparse_f64
+ *   n_primes          0 = choose from the Bregman bound (at least 3), else 1..5
+ *   out_limbs         host uint64[5]: perm as unsigned little-endian 320 bits
+ *   out_residues      host uint64[n_primes used] or NULL: perm mod p_k
+ * Synchronises `stream`.  PERM_ERANGE if the bound exceeds the modulus.
+ */
+int perm_binary_exact(int n, const int32_t *col_ptr, const int32_t *row_idx,
+                      int32_t nnz, int n_primes, uint64_t out_limbs[5],
+                      uint64_t *out_residues, void *ws, size_t ws_bytes,
+                      void *stream);
+
+/* The k-th prime used by perm_binary_exact (k = 0..4), 0 if out of range. */
+uint64_t perm_binary_prime(int k);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PERM_MI355X_H */

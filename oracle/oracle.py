@@ -59,6 +59,8 @@ def _declare(lib):
         f = getattr(lib, name)
         f.restype = c_int
         f.argtypes = [c_int, dp, c_int, dp, dp]
+    lib.orc_ryser_real_sample.restype = c_int
+    lib.orc_ryser_real_sample.argtypes = [c_int, dp, c_int, ctypes.c_uint64, ctypes.c_uint64, dp]
     lib.orc_sparyser_real.restype = c_int
     lib.orc_sparyser_real.argtypes = [c_int, i32p, i32p, dp, i32p, i32p, dp, dp]
     lib.orc_ryser_binary.restype = c_int
@@ -168,6 +170,17 @@ class Oracle:
         if with_abs:
             return val, float(absum[0] + absum[1])
         return val
+
+    def ryser_sample(self, a, first_chunk: int, nchunks: int, threads: int = 0) -> float:
+        """Unscaled partial sum of Algorithm 1 over chunks of 4096 steps
+        [first_chunk, first_chunk + nchunks) -- for timing samples only."""
+        r = _real(a)
+        out = np.zeros(2)
+        _check(self.lib.orc_ryser_real_sample(r.shape[0], _dptr(r), threads, first_chunk, nchunks,
+                                              _dptr(out)), "ryser_real_sample")
+        return float(out[0] + out[1])
+
+    CHUNK_STEPS = 4096
 
     # -- Algorithm 2 ----------------------------------------------------------
     def sparyser(self, a):

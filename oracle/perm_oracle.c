@@ -249,6 +249,7 @@ typedef struct {
     uint64_t nitems, chunks_per_item;
     ld *item_re, *item_im, *item_abs;
     uint64_t next_item;     /* atomic work counter */
+    uint64_t first_chunk;   /* chunk index of item 0 (0 except for samples) */
 } ryser_job_t;
 
 static void ryser_range(const ryser_job_t *J, uint64_t start, uint64_t end,
@@ -311,7 +312,7 @@ static void *ryser_worker(void *arg)
         if (it >= J->nitems) break;
         kahan_t kre = {0, 0}, kim = {0, 0};
         ld abs_sum = 0;
-        uint64_t c0 = it * J->chunks_per_item;
+        uint64_t c0 = J->first_chunk + it * J->chunks_per_item;
         for (uint64_t c = c0; c < c0 + J->chunks_per_item; c++) {
             uint64_t start = c * ORC_CHUNK + 1;
             if (start > J->steps) break;
@@ -423,6 +424,52 @@ int orc_ryser_real(int n, const double *a, int nthreads, double out[2], double a
 int orc_ryser_cplx(int n, const double *a, int nthreads, double out[4], double absum[2])
 {
     return ryser_common(n, a, 1, nthreads, out, absum);
+}
+
+/* Partial sum of Algorithm 1 over the chunks [first_chunk, first_chunk +
+ * nchunks) of ORC_CHUNK steps each (no final scaling, no g = 0 term).  Used
+ * only to time the oracle on a bounded sample of a large workload. */
+int orc_ryser_real_sample(int n, const double *a, int nthreads, uint64_t first_chunk,
+                          uint64_t nchunks, double out[2])
+{
+    if (n < 2 || n > 63 || !a || !out) return -1;
+    ld x0r[64], x0i[64];
+    for (int i = 0; i < n; i++) {
+        ld sr = 0;
+        for (int j = 0; j < n; j++) sr += a[i * n + j];
+        x0r[i] = a[i * n + n - 1] - sr / 2;
+        x0i[i] = 0;
+    }
+    ryser_job_t J;
+    memset(&J, 0, sizeof J);
+    J.n = n; J.cplx = 0; J.a = a; J.x0r = x0r; J.x0i = x0i;
+    J.steps = (1ull << (n - 1)) - 1;
+    uint64_t total_chunks = (J.steps + ORC_CHUNK - 1) / ORC_CHUNK;
+    if (first_chunk >= total_chunks) return -1;
+    if (first_chunk + nchunks > total_chunks) nchunks = total_chunks - first_chunk;
+    /* one work item per chunk of the sample, offset by first_chunk */
+    J.chunks_per_item = 1;
+    J.nitems = nchunks;
+    J.item_re = (ld *)calloc(nchunks ? nchunks : 1, sizeof(ld));
+    J.item_im = (ld *)calloc(nchunks ? nchunks : 1, sizeof(ld));
+    J.item_abs = (ld *)calloc(nchunks ? nchunks : 1, sizeof(ld));
+    if (!J.item_re || !J.item_im || !J.item_abs) {
+        free(J.item_re); free(J.item_im); free(J.item_abs);
+        return -1;
+    }
+    J.first_chunk = first_chunk;
+    int T = default_threads(nthreads);
+    if (T > 256) T = 256;
+    pthread_t th[256];
+    int ok[256] = {0};
+    for (int t = 1; t < T; t++) ok[t] = pthread_create(&th[t], NULL, ryser_worker, &J) == 0;
+    ryser_worker(&J);
+    for (int t = 1; t < T; t++) if (ok[t]) pthread_join(th[t], NULL);
+    kahan_t k = {0, 0};
+    for (uint64_t it = 0; it < J.nitems; it++) kahan_add(&k, J.item_re[it]);
+    free(J.item_re); free(J.item_im); free(J.item_abs);
+    ld_split(k.s - k.c, out);
+    return 0;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -1,0 +1,89 @@
+// Internal declarations shared by the host ABI layer and the HIP kernels of
+// libperm_mi355x.so.  Not part of the public ABI (that is include/perm.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "perm.h"
+
+namespace perm {
+
+// ---------------------------------------------------------------------------
+// Launch shape
+// ---------------------------------------------------------------------------
+constexpr int kBlock = 256;          // threads per block: 4 waves of 64
+constexpr int kWave = 64;
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr int kSerialMaxN = 8;       // n <= 8: 2^(n-1) <= 128 steps, one lane
+
+// Gray-walk decomposition of the 2^(n-1) steps of one matrix:
+//   lanes * 2^log2_chunk == 2^(n-1), every lane walks one contiguous chunk,
+//   and x is rebuilt exactly from the Gray code every 2^log2_reseed steps.
+struct SweepPlan {
+    int n = 0;
+    int log2_chunk = 0;      // c: steps per lane = 2^c (c >= 2)
+    int log2_reseed = 0;     // r: exact re-seed every 2^r steps (1 <= r <= c)
+    int64_t lanes = 0;       // 2^(n-1-c), a multiple of 128 (whole wave pairs)
+    int64_t blocks = 0;      // lanes / kBlock (rounded up)
+};
+
+SweepPlan plan_sweep(int n, int steps_per_op_hint);
+
+// ---------------------------------------------------------------------------
+// Double-double helpers (error-free transformations; require IEEE
+// round-to-nearest and no reassociation, which hipcc gives without
+// -ffast-math).
+// ---------------------------------------------------------------------------
+struct dd {
+    double hi, lo;
+};
+
+__host__ __device__ inline void two_sum(double a, double b, double &s, double &e)
+{
+    s = a + b;
+    double bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+// Sum of two double-double values (accurate to about 2^-104 relative).
+__host__ __device__ inline dd dd_add(dd a, dd b)
+{
+    double s, e;
+    two_sum(a.hi, b.hi, s, e);
+    double t, f;
+    two_sum(a.lo, b.lo, t, f);
+    e += t;
+    double hi = s + e;
+    double lo = e - (hi - s);
+    lo += f;
+    double hi2 = hi + lo;
+    return dd{hi2, lo - (hi2 - hi)};
+}
+
+// ---------------------------------------------------------------------------
+// Workspace layouts (byte offsets into the caller's device workspace)
+// ---------------------------------------------------------------------------
+inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+struct DenseWs {
+    size_t acol = 0;      // n*n scalars, column-major copy of A
+    size_t aneg = 0;      // n*n scalars, its negation
+    size_t x0 = 0;        // n scalars, Nijenhuis-Wilf start vector
+    size_t partials = 0;  // one dd (per component) per block
+    size_t total = 0;
+};
+
+DenseWs dense_ws_layout(int n, int components, int64_t blocks);
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (defined in the .hip files).  All return PERM_OK or
+// PERM_EHIP and only enqueue work on `stream`.
+// ---------------------------------------------------------------------------
+int launch_dense_f64(int n, const double *A, int64_t lda, double *out, char *ws,
+                     hipStream_t stream);
+int launch_dense_c128(int n, const perm_c128 *A, int64_t lda, perm_c128 *out, char *ws,
+                      hipStream_t stream);
+
+}  // namespace perm

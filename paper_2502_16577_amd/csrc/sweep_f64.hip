@@ -1,0 +1,211 @@
+// Dense real FP64 permanent: the Gray-code Ryser / Nijenhuis-Wilf sweep
+// (Algorithm 1 of arXiv 2502.16577, chunked as in Algorithm 3 with the
+// power-of-two chunks of Section 3.2).
+//
+// Data layout in HBM (all inside the caller's workspace):
+//   acol[j*N + i] = a_ij   (column-major, so one Gray step reads one
+//   aneg[j*N + i] = -a_ij   contiguous column; the sign picks the copy)
+//   x0[i] = a_{i,n-1} - r_i/2
+//   partials[b] = double-double sum of block b
+//
+// Per lane: x[N] lives in VGPRs (N is a template parameter, the analogue of
+// the paper's per-matrix rebuild of Section 3.3).  Because the chunk length is
+// a power of two and bit 0 of the chunk index is shared by the whole wave,
+// the flipped column j = ctz(l) and its sign are wave-uniform at every step,
+// so the column is fetched with scalar loads into SGPRs and feeds v_add_f64
+// directly: no LDS traffic and no per-lane addressing in the hot loop.
+#include "sweep_common.h"
+
+namespace perm {
+
+__global__ __launch_bounds__(kBlock) void prep_dense_f64(int n, const double *__restrict__ A,
+                                                         int64_t lda, double *__restrict__ acol,
+                                                         double *__restrict__ aneg,
+                                                         double *__restrict__ x0)
+{
+    for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+        const int j = idx / n;
+        const int i = idx - j * n;
+        const double v = A[int64_t(i) * lda + j];
+        acol[idx] = v;
+        aneg[idx] = -v;
+    }
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        double s = 0.0, e = 0.0;  // compensated row sum r_i = s + e
+        for (int j = 0; j < n; ++j) acc_add(s, e, A[int64_t(i) * lda + j]);
+        x0[i] = (A[int64_t(i) * lda + n - 1] - 0.5 * s) - 0.5 * e;
+    }
+}
+
+// n <= kSerialSmallN: one lane runs Algorithm 1 directly (at most 2^11 steps).
+constexpr int kSerialSmallN = 12;
+
+__global__ void serial_dense_f64(int n, const double *__restrict__ acol,
+                                 const double *__restrict__ aneg,
+                                 const double *__restrict__ x0, dd *__restrict__ partials)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double x[kSerialSmallN];
+    for (int i = 0; i < n; ++i) x[i] = x0[i];
+    double s = 0.0, e = 0.0;
+    double p = 1.0;
+    for (int i = 0; i < n; ++i) p *= x[i];
+    acc_add(s, e, p);
+    const uint32_t steps = 1u << (n - 1);
+    for (uint32_t g = 1; g < steps; ++g) {
+        const int j = __builtin_ctz(g);
+        const bool add = ((g ^ (g >> 1)) >> j) & 1u;
+        const double *a = (add ? acol : aneg) + j * n;
+        p = 1.0;
+        for (int i = 0; i < n; ++i) {
+            x[i] += a[i];
+            p *= x[i];
+        }
+        acc_add(s, e, (g & 1u) ? -p : p);
+    }
+    partials[0] = dd{s, e};
+}
+
+template <int N>
+__device__ __forceinline__ double product4(const double (&x)[N])
+{
+    static_assert(N >= 4, "product4 needs N >= 4");
+    double p0 = x[0], p1 = x[1], p2 = x[2], p3 = x[3];
+#pragma unroll
+    for (int i = 4; i < N; i += 4) {
+        p0 *= x[i];
+        if (i + 1 < N) p1 *= x[i + 1];
+        if (i + 2 < N) p2 *= x[i + 2];
+        if (i + 3 < N) p3 *= x[i + 3];
+    }
+    return (p0 * p1) * (p2 * p3);
+}
+
+template <int N>
+__device__ __forceinline__ void add_column(double (&x)[N], const double *__restrict__ a)
+{
+#pragma unroll
+    for (int i = 0; i < N; ++i) x[i] += a[i];
+}
+
+// x = x0 + sum of the columns in the Gray code of step l of this lane's
+// chunk: the lane-specific columns j >= c (bits `hbits`) and the
+// wave-uniform columns j < c (bits `low`).
+template <int N>
+__device__ __forceinline__ void reseed(double (&x)[N], const double *__restrict__ acol,
+                                       const double *__restrict__ x0, uint64_t hbits,
+                                       uint32_t low, int c)
+{
+#pragma unroll
+    for (int i = 0; i < N; ++i) x[i] = x0[i];
+    for (int j = c; j < N - 1; ++j) {
+        const double f = ((hbits >> (j - c)) & 1u) ? 1.0 : 0.0;
+        const double *a = acol + j * N;
+#pragma unroll
+        for (int i = 0; i < N; ++i) x[i] = __builtin_fma(f, a[i], x[i]);
+    }
+    while (low) {
+        const int j = __builtin_ctz(low);
+        low &= low - 1u;
+        add_column<N>(x, acol + j * N);
+    }
+}
+
+template <int N>
+__global__ __launch_bounds__(kBlock) void sweep_dense_f64(const double *__restrict__ acol,
+                                                          const double *__restrict__ aneg,
+                                                          const double *__restrict__ x0,
+                                                          dd *__restrict__ partials, int c, int r)
+{
+    __shared__ dd red[kWavesPerBlock];
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t wave = uniform_wave_index();
+    const uint64_t K = lane_chunk_index(wave, lane);
+    const uint32_t kb = uint32_t(wave & 1u);
+    const uint64_t g0 = K << c;
+    const uint64_t hbits = (g0 ^ (g0 >> 1)) >> c;
+    const uint32_t C = 1u << c;
+    const uint32_t rmask = (1u << r) - 1u;
+
+    double x[N];
+    double s = 0.0, e = 0.0;
+    for (uint32_t l = 0; l < C; l += 2) {
+        // even step l: re-seed exactly, or flip column ctz(l)
+        if ((l & rmask) == 0) {
+            reseed<N>(x, acol, x0, hbits, gray_low(l, kb, c), c);
+        } else {
+            const int j = __builtin_ctz(l);
+            const bool add = (gray_low(l, kb, c) >> j) & 1u;
+            add_column<N>(x, (add ? acol : aneg) + j * N);
+        }
+        const double t_even = product4<N>(x);
+        // odd step l + 1: always flips column 0
+        const bool add0 = gray_low(l + 1, kb, c) & 1u;
+        add_column<N>(x, add0 ? acol : aneg);
+        const double t_odd = product4<N>(x);
+        // (-1)^g = (-1)^l since every chunk starts at an even g
+        acc_add(s, e, t_even - t_odd);
+    }
+    const dd t = block_reduce_dd(dd{s, e}, red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+template <int N>
+static void launch_sweep_n(const SweepPlan &p, const double *acol, const double *aneg,
+                           const double *x0, dd *partials, hipStream_t stream)
+{
+    hipLaunchKernelGGL(sweep_dense_f64<N>, dim3(unsigned(p.blocks)), dim3(kBlock), 0, stream,
+                       acol, aneg, x0, partials, p.log2_chunk, p.log2_reseed);
+}
+
+using SweepLauncher = void (*)(const SweepPlan &, const double *, const double *, const double *,
+                               dd *, hipStream_t);
+
+template <int... Ns>
+struct SweepTable {
+    static SweepLauncher get(int n)
+    {
+        SweepLauncher f = nullptr;
+        ((n == Ns ? (f = &launch_sweep_n<Ns>, 0) : 0), ...);
+        return f;
+    }
+};
+
+using DenseF64Table =
+    SweepTable<13, 14, 15, 16, 17, 18, 19, 20, 21, 22, 23, 24, 25, 26, 27, 28, 29, 30, 31, 32, 33,
+               34, 35, 36, 37, 38, 39, 40, 41, 42, 43, 44, 45, 46, 47, 48, 49, 50, 51, 52, 53, 54,
+               55, 56, 57, 58, 59, 60, 61, 62, 63>;
+
+__global__ void write_one_f64(double *out) { out[0] = 1.0; }
+
+int launch_dense_f64(int n, const double *A, int64_t lda, double *out, char *ws,
+                     hipStream_t stream)
+{
+    if (n == 0) {
+        hipLaunchKernelGGL(write_one_f64, dim3(1), dim3(1), 0, stream, out);
+        return hipGetLastError() == hipSuccess ? PERM_OK : PERM_EHIP;
+    }
+    const SweepPlan p = plan_sweep(n, 0);
+    const DenseWs L = dense_ws_layout(n, 1, p.blocks);
+    double *acol = reinterpret_cast<double *>(ws + L.acol);
+    double *aneg = reinterpret_cast<double *>(ws + L.aneg);
+    double *x0 = reinterpret_cast<double *>(ws + L.x0);
+    dd *partials = reinterpret_cast<dd *>(ws + L.partials);
+    hipLaunchKernelGGL(prep_dense_f64, dim3(1), dim3(kBlock), 0, stream, n, A, lda, acol, aneg, x0);
+    int64_t nparts = 1;
+    if (n <= kSerialSmallN) {
+        hipLaunchKernelGGL(serial_dense_f64, dim3(1), dim3(64), 0, stream, n, acol, aneg, x0,
+                           partials);
+    } else {
+        SweepLauncher f = DenseF64Table::get(n);
+        if (!f) return PERM_EUNSUPPORTED;
+        f(p, acol, aneg, x0, partials, stream);
+        nparts = p.blocks;
+    }
+    const double scale = (n & 1) ? 2.0 : -2.0;  // 2 (-1)^(n-1)
+    hipLaunchKernelGGL(finalize_partials, dim3(1), dim3(kBlock), 0, stream, partials, nparts, 1,
+                       scale, out);
+    return hipGetLastError() == hipSuccess ? PERM_OK : PERM_EHIP;
+}
+
+}  // namespace perm

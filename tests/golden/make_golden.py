@@ -1,0 +1,73 @@
+"""Writes the oracle's values for the full-size workloads to full_size.json.
+
+Run from the repository root:  python tests/golden/make_golden.py [names...]
+
+Every stored value comes from ``oracle/`` (long double Ryser, exact integer
+Ryser); the inputs come from the seeded generators, and each entry records the
+sha256 of its input so a test can refuse a value whose input drifted.  The
+script updates entries in place, so it can be rerun for a subset of names.
+"""
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+from oracle.oracle import default  # noqa: E402
+from paper_2502_16577_amd import workloads as W  # noqa: E402
+
+OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "full_size.json")
+
+
+def inputs():
+    return {
+        "u20": lambda: W.uniform(20, W.SEED_U20),
+        "u32": lambda: W.uniform(32, W.SEED_U32),
+        "rademacher32": lambda: W.rademacher(32, W.SEED_RADEMACHER32),
+        "haar30": lambda: W.haar_block(120, 30, W.SEED_HAAR120),
+        "bernoulli32": lambda: W.bernoulli(32, W.SEED_BERNOULLI32),
+        "sparse40": lambda: W.sparse_rows(40, 6, W.SEED_SPARSE40),
+    }
+
+
+def run(name, a, orc):
+    t0 = time.time()
+    rec = {"digest": W.digest(a), "n": int(a.shape[0]), "threads": os.cpu_count()}
+    if a.dtype == np.uint8:
+        v, nz = orc.binary(a, with_nonzero=True)
+        rec.update(kind="binary", value=str(v), nonzero_terms=nz)
+    elif np.iscomplexobj(a):
+        (rh, rl, ih, il), r = orc.ryser(a, with_abs=True, split=True)
+        rec.update(kind="complex", re=[rh, rl], im=[ih, il], abs_sum=r,
+                   abs_perm=orc.ryser(np.abs(a)))
+    else:
+        (h, l), r = orc.ryser(a, with_abs=True, split=True)
+        rec.update(kind="real", value=[h, l], abs_sum=r, abs_perm=orc.ryser(np.abs(a)))
+    rec["oracle_seconds"] = round(time.time() - t0, 2)
+    return rec
+
+
+def main(names):
+    gens = inputs()
+    names = names or list(gens)
+    data = {}
+    if os.path.exists(OUT):
+        with open(OUT) as f:
+            data = json.load(f)
+    orc = default()
+    for name in names:
+        a = gens[name]()
+        rec = run(name, a, orc)
+        data[name] = rec
+        with open(OUT, "w") as f:
+            json.dump(data, f, indent=1, sort_keys=True)
+        print(name, rec, flush=True)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])

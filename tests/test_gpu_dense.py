@@ -1,0 +1,126 @@
+"""Parity of the dense HIP sweeps (real and complex) with the CPU oracle.
+
+Tolerances: relative 1e-10 for U[0,1) entries; for signed or complex
+entries |gpu - oracle| <= 1e-10 * perm(|A|) and, because that bound is loose
+at these sizes, also |gpu - oracle| <= 1e-13 * R(A), where R(A) is the
+oracle's Ryser absolute sum 2 * sum_g |prod_i x_i(g)| (the natural scale of
+the rounding error of any evaluation of the Ryser sum).
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2502_16577_amd import api
+from paper_2502_16577_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "full_size.json")
+DEV = torch.device("cuda:0")
+
+
+def gpu_perm(a):
+    return api.perm(torch.from_numpy(np.ascontiguousarray(a)).to(DEV)).cpu().item()
+
+
+def derangements(n):
+    d = [1, 0]
+    for k in range(2, n + 1):
+        d.append((k - 1) * (d[k - 1] + d[k - 2]))
+    return d[n]
+
+
+@pytest.mark.parametrize("n", list(range(0, 25)))
+def test_uniform_small(oracle, n):
+    a = W.uniform(n, 500 + n)
+    got = gpu_perm(a)
+    want = oracle.perm(a) if n else 1.0
+    assert abs(got - want) <= 1e-10 * abs(want), (n, got, want)
+
+
+@pytest.mark.parametrize("n", [1, 5, 9, 12, 13, 14, 16, 19, 22, 24])
+def test_signed_small(oracle, n):
+    a = np.random.default_rng(600 + n).standard_normal((n, n))
+    got = gpu_perm(a)
+    want, r = oracle.ryser(a, with_abs=True)
+    assert abs(got - want) <= 1e-10 * oracle.ryser(np.abs(a))
+    assert abs(got - want) <= 1e-13 * r, (n, got, want, r)
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 12, 13, 15, 18, 21])
+def test_complex_small(oracle, n):
+    a = W.haar_block(max(2 * n, 2), n, 700 + n)
+    got = complex(api.perm(torch.from_numpy(a).to(DEV)).cpu().item())
+    want, r = oracle.ryser(a, with_abs=True)
+    assert abs(got - want) <= 1e-10 * oracle.ryser(np.abs(a))
+    assert abs(got - want) <= 1e-13 * r, (n, got, want, r)
+
+
+def test_closed_forms_n20():
+    assert gpu_perm(W.all_ones(20)) == pytest.approx(math.factorial(20), rel=1e-13)
+    assert gpu_perm(W.ones_minus_identity(20)) == pytest.approx(derangements(20), rel=1e-13)
+    assert gpu_perm(np.eye(20)) == pytest.approx(1.0, rel=1e-14)
+    d = np.linspace(0.5, 1.5, 20)
+    assert gpu_perm(np.diag(d)) == pytest.approx(float(np.prod(d)), rel=1e-13)
+
+
+def test_all_equal_n_closed_form(oracle):
+    # Section 5: all entries a -> n! a^n (the paper's own precision test).
+    # These matrices cancel heavily (R(A) / perm = 5.7e3 at n = 26, 2.8e4 at
+    # n = 30) and all rows are equal, so rounding errors are correlated: gate
+    # on relative 1e-10 and on the forward-error model |err| <= 2 n u R(A).
+    for n in (26, 30):
+        a = np.full((n, n), 0.91)
+        exact = math.factorial(n) * 0.91 ** n
+        _, r = oracle.ryser(a, with_abs=True)
+        got = gpu_perm(a)
+        assert abs(got - exact) <= 1e-10 * exact, (n, got, exact)
+        assert abs(got - exact) <= 2 * n * 2.0 ** -53 * r, (n, got, exact, r)
+
+
+def test_strided_rows():
+    big = W.uniform(24, 3)
+    sub = torch.from_numpy(big).to(DEV)[:18, :18]
+    ref = api.perm(sub.contiguous()).item()
+    assert api.perm(sub).item() == ref
+
+
+def test_deterministic():
+    a = torch.from_numpy(W.uniform(27, 9)).to(DEV)
+    assert api.perm(a).item() == api.perm(a).item()
+
+
+def _golden(name):
+    with open(GOLDEN) as f:
+        return json.load(f)[name]
+
+
+@pytest.mark.parametrize("name,gen", [
+    ("u20", lambda: W.uniform(20, W.SEED_U20)),
+    ("u32", lambda: W.uniform(32, W.SEED_U32)),
+    ("rademacher32", lambda: W.rademacher(32, W.SEED_RADEMACHER32)),
+])
+def test_full_size_real(name, gen):
+    g = _golden(name)
+    a = gen()
+    assert W.digest(a) == g["digest"], "input generator drifted from the stored oracle value"
+    want = g["value"][0] + g["value"][1]
+    got = gpu_perm(a)
+    if name.startswith("u"):
+        assert abs(got - want) <= 1e-10 * abs(want), (got, want)
+    else:
+        assert abs(got - want) <= 1e-10 * g["abs_perm"]
+        assert abs(got - want) <= 1e-13 * g["abs_sum"], (got, want)
+
+
+def test_full_size_haar30():
+    g = _golden("haar30")
+    a = W.haar_block(120, 30, W.SEED_HAAR120)
+    assert W.digest(a) == g["digest"]
+    want = complex(g["re"][0] + g["re"][1], g["im"][0] + g["im"][1])
+    got = complex(api.perm(torch.from_numpy(a).to(DEV)).cpu().item())
+    assert abs(got - want) <= 1e-10 * g["abs_perm"]
+    assert abs(got - want) <= 1e-13 * g["abs_sum"], (got, want)
