@@ -35,6 +35,20 @@ N = 32
 PEAK_ALU_TFLOPS = 256 * 64 * 2.4e9 / 1e12      # 39.32: one add or mul per lane per clock
 PEAK_FMA_TFLOPS = 78.6                           # published FP64 vector peak (FMA = 2 flops)
 
+# HBM bytes per sweep launch from rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by a
+# plain 1 GiB copy (profiles/sweep_dense_f64_n32_u01.md).  Valid only for the
+# kernel source they were measured on; reported as null once it changes.
+COUNTERS_SRC = os.path.join(ROOT, "paper_2502_16577_amd", "csrc", "sweep_f64.hip")
+COUNTERS_SRC_SHA256 = "af1ec4abc621ea97686c7d830e2358ecf6088956e2f2249399d83ec21ca7e5da"
+TRAFFIC_BYTES_PER_LAUNCH = 124 * 1024 * 2.000 + 32 * 1024 * 1.000
+
+
+def traffic_bytes():
+    import hashlib
+    with open(COUNTERS_SRC, "rb") as f:
+        ok = hashlib.sha256(f.read()).hexdigest() == COUNTERS_SRC_SHA256
+    return TRAFFIC_BYTES_PER_LAUNCH if ok else None
+
 
 def cpu_baseline(a, target_seconds=12.0):
     from oracle.oracle import default
@@ -59,10 +73,24 @@ def cpu_baseline(a, target_seconds=12.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (3 times) and exit; "
+                         "used to scale FETCH_SIZE / WRITE_SIZE counters to bytes")
     args = ap.parse_args()
+    if args.calibrate_copy_mib:
+        import torch
+        nbytes = args.calibrate_copy_mib << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read_per_launch": nbytes,
+                          "copy_bytes_written_per_launch": nbytes, "launches": 3}))
+        return
     if args.gpus != 1:
         print("bench.py: this build runs on exactly one GPU (no multi-GPU path); use --gpus 1",
               file=sys.stderr)
@@ -116,7 +144,7 @@ def main():
                                "one perm_dense_f64 call = 2^31 subset-steps",
                    "n": N, "subset_steps_per_step": steps_per_call},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_ALU_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_ALU_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_ALU_TFLOPS, "traffic": traffic_bytes(),
                      "kernel": "sweep_dense_f64<32>", "event_ms_per_launch": avg_ms,
                      "flops_per_subset_step": 2 * N + 2,
                      "frac_of_published_fp64_peak_78.6": achieved / PEAK_FMA_TFLOPS},
