@@ -22,7 +22,8 @@
  *     and keeps no pointer after a call returns.
  *   - stream is a hipStream_t passed as void* (NULL = the null stream).  All
  *     calls are asynchronous on that stream except perm_binary_exact, which
- *     synchronises it to finish the Chinese remaindering on the host.
+ *     synchronises it to finish the Chinese remaindering on the host, and
+ *     perm_sparse_f64, which synchronises it once its host pattern is staged.
  *   - Results are deterministic for fixed inputs and sizes: partial sums are
  *     combined in a fixed order and no result goes through atomics.
  *   - n == 0 yields 1 (the empty product); n < 0 or n > PERM_MAX_N is
@@ -100,9 +101,12 @@ int perm_dense_c128(int n, const perm_c128 *A, int64_t lda, perm_c128 *out,
                     void *ws, size_t ws_bytes, void *stream);
 
 /*
- * Permanent of a sparse real n x n matrix in CSC (Algorithm 2, SpaRyser): a
- * Gray step updates only the rows of column j that hold nonzeros; the product
- * still runs over all n rows.
+ * Permanent of a sparse real n x n matrix in CSC (Algorithm 2, SpaRyser:
+ * the same Gray walk, a step adds the nonzeros of one column to x, and the
+ * product runs over all n rows).  The pattern is validated on the host and
+ * staged into the workspace as column copies; the call returns once the
+ * staging copy has completed (it synchronises `stream`), and the sweep then
+ * runs asynchronously.
  *   col_ptr  host int32[n+1], col_ptr[0] = 0, nondecreasing, col_ptr[n] = nnz
  *   row_idx  host int32[nnz], strictly increasing within a column, in [0, n)
  *   vals     host double[nnz]
@@ -120,13 +124,17 @@ int perm_sparse_f64(int n, const int32_t *col_ptr, const int32_t *row_idx,
  *   col_ptr, row_idx  host CSC pattern as for perm_sparse_f64
  *   n_primes          0 = choose from the Bregman bound (at least 3), else 1..5
  *   out_limbs         host uint64[5]: perm as unsigned little-endian 320 bits
- *   out_residues      host uint64[n_primes used] or NULL: perm mod p_k
- * Synchronises `stream`.  PERM_ERANGE if the bound exceeds the modulus.
+ *   out_residues      host uint64[5] or NULL: perm mod p_k for the primes
+ *                     used, zero in the unused slots
+ *   out_nprimes       host int or NULL: number of primes used
+ * Synchronises `stream`.  PERM_ERANGE if the bound exceeds the modulus of
+ * the requested primes.  A matrix with an empty row or column has permanent
+ * 0 and launches nothing.
  */
 int perm_binary_exact(int n, const int32_t *col_ptr, const int32_t *row_idx,
                       int32_t nnz, int n_primes, uint64_t out_limbs[5],
-                      uint64_t *out_residues, void *ws, size_t ws_bytes,
-                      void *stream);
+                      uint64_t *out_residues, int *out_nprimes, void *ws,
+                      size_t ws_bytes, void *stream);
 
 /* The k-th prime used by perm_binary_exact (k = 0..4), 0 if out of range. */
 uint64_t perm_binary_prime(int k);

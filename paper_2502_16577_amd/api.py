@@ -71,8 +71,75 @@ def perm_dense_c128(A: torch.Tensor, out: torch.Tensor | None = None, ws=None) -
     return out
 
 
+def perm_sparse_f64(n: int, col_ptr, row_idx, vals, device="cuda:0", out=None, ws=None):
+    """Permanent of a sparse real matrix given in CSC on the host."""
+    col_ptr = np.ascontiguousarray(col_ptr, dtype=np.int32)
+    row_idx = np.ascontiguousarray(row_idx, dtype=np.int32)
+    vals = np.ascontiguousarray(vals, dtype=np.float64)
+    device = torch.device(device)
+    nnz = int(row_idx.size)
+    if out is None:
+        out = torch.empty((), dtype=torch.float64, device=device)
+    ws, need = _workspace(N.KIND_SPARSE_F64, n, nnz, device, ws)
+    st = N.lib().perm_sparse_f64(n, col_ptr.ctypes.data if n else None,
+                                 row_idx.ctypes.data if nnz else None,
+                                 vals.ctypes.data if nnz else None, nnz, out.data_ptr(),
+                                 ws.data_ptr(), need, _stream(device))
+    N.check(st, "perm_sparse_f64")
+    return out
+
+
 def perm(A: torch.Tensor) -> torch.Tensor:
     """Permanent of a dense float64 or complex128 CUDA matrix."""
     if A.dtype == torch.complex128:
         return perm_dense_c128(A)
     return perm_dense_f64(A)
+
+
+def _csc_of(a01):
+    """CSC pattern (col_ptr, row_idx) of a square 0/1 matrix (host)."""
+    a = np.asarray(a01.cpu() if isinstance(a01, torch.Tensor) else a01)
+    if a.ndim != 2 or a.shape[0] != a.shape[1]:
+        raise ValueError("square matrix expected")
+    if not np.all((a == 0) | (a == 1)):
+        raise ValueError("0/1 entries expected")
+    n = a.shape[0]
+    col_ptr = np.zeros(n + 1, np.int32)
+    rows = []
+    for j in range(n):
+        nz = np.nonzero(a[:, j])[0]
+        rows.extend(int(r) for r in nz)
+        col_ptr[j + 1] = len(rows)
+    return n, col_ptr, np.array(rows, np.int32)
+
+
+def perm_binary_exact(a01=None, *, csc=None, n_primes: int = 0, device="cuda:0", ws=None):
+    """Exact permanent of a 0/1 matrix (dense 0/1 array or csc=(n, col_ptr, row_idx)).
+
+    Returns (value as Python int, list of residues perm mod p_k)."""
+    if csc is None:
+        n, col_ptr, row_idx = _csc_of(a01)
+    else:
+        n, col_ptr, row_idx = csc
+        col_ptr = np.ascontiguousarray(col_ptr, dtype=np.int32)
+        row_idx = np.ascontiguousarray(row_idx, dtype=np.int32)
+    device = torch.device(device)
+    ws, need = _workspace(N.KIND_BINARY, n, 0, device, ws)
+    limbs = np.zeros(5, np.uint64)
+    res = np.zeros(5, np.uint64)
+    used = ctypes.c_int(0)
+    nnz = int(row_idx.size)
+    st = N.lib().perm_binary_exact(
+        n, col_ptr.ctypes.data if n else None,
+        row_idx.ctypes.data if nnz else None, nnz, n_primes,
+        limbs.ctypes.data, res.ctypes.data, ctypes.byref(used), ws.data_ptr(), need,
+        _stream(device))
+    N.check(st, "perm_binary_exact")
+    value = 0
+    for k in range(4, -1, -1):
+        value = (value << 64) | int(limbs[k])
+    return value, [int(r) for r in res[:used.value]]
+
+
+def binary_prime(k: int) -> int:
+    return int(N.lib().perm_binary_prime(k))

@@ -4,7 +4,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
+#include <vector>
 
 #include "perm.h"
 #include "perm_internal.h"
@@ -54,6 +56,32 @@ DenseWs dense_ws_layout(int n, int components, int64_t blocks)
     return L;
 }
 
+BinaryWs binary_ws_layout(int n, int64_t blocks)
+{
+    BinaryWs L;
+    size_t off = 0;
+    const size_t nn = size_t(n) * size_t(n) * sizeof(double);
+    L.dense01 = off;
+    off += align256(nn);
+    L.ycol = off;
+    off += align256(nn);
+    L.yneg = off;
+    off += align256(nn);
+    L.y0 = off;
+    off += align256(size_t(n) * sizeof(double));
+    L.partials = off;
+    off += align256(size_t(std::max<int64_t>(blocks, 1)) * kMaxPrimes * sizeof(uint64_t));
+    L.residues = off;
+    off += align256(kMaxPrimes * sizeof(uint64_t));
+    L.total = off;
+    return L;
+}
+
+// Host copy of the primes 2^61 - c used by the binary kernels.
+constexpr uint64_t kPrimeCHost[kMaxPrimes] = {1, 31, 45, 229, 259};
+
+uint64_t host_prime(int k) { return (uint64_t(1) << 61) - kPrimeCHost[k]; }
+
 }  // namespace perm
 
 using namespace perm;
@@ -61,6 +89,49 @@ using namespace perm;
 namespace {
 
 bool valid_n(int n) { return n >= 0 && n <= PERM_MAX_N; }
+
+// CSC pattern checks: col_ptr[0] = 0, nondecreasing, col_ptr[n] = nnz, row
+// indices in [0, n) and strictly increasing inside each column.
+bool valid_csc(int n, const int32_t *col_ptr, const int32_t *row_idx, int32_t nnz)
+{
+    if (!col_ptr || nnz < 0 || (nnz > 0 && !row_idx)) return false;
+    if (int64_t(nnz) > int64_t(n) * n) return false;
+    if (col_ptr[0] != 0 || col_ptr[n] != nnz) return false;
+    for (int j = 0; j < n; ++j) {
+        if (col_ptr[j + 1] < col_ptr[j]) return false;
+        for (int32_t p = col_ptr[j]; p < col_ptr[j + 1]; ++p) {
+            if (row_idx[p] < 0 || row_idx[p] >= n) return false;
+            if (p > col_ptr[j] && row_idx[p] <= row_idx[p - 1]) return false;
+        }
+    }
+    return true;
+}
+
+uint64_t mulmod_host(uint64_t a, uint64_t b, uint64_t p)
+{
+    return uint64_t((unsigned __int128)a * b % p);
+}
+
+uint64_t powmod_host(uint64_t a, uint64_t e, uint64_t p)
+{
+    uint64_t r = 1 % p;
+    a %= p;
+    while (e) {
+        if (e & 1) r = mulmod_host(r, a, p);
+        a = mulmod_host(a, a, p);
+        e >>= 1;
+    }
+    return r;
+}
+
+// log2 of the Bregman-Minc bound prod_i (r_i!)^(1/r_i) on the permanent of a
+// 0/1 matrix with row sums r_i (all r_i >= 1).
+double bregman_log2(const std::vector<int> &r)
+{
+    double b = 0.0;
+    for (int ri : r) b += std::lgamma(double(ri) + 1.0) / std::log(2.0) / double(ri);
+    return b;
+}
 
 int check_ws(const void *ws, size_t ws_bytes, size_t need)
 {
@@ -101,6 +172,14 @@ size_t perm_workspace_bytes(int kind, int n, int64_t m)
         const SweepPlan p = plan_sweep(n, 0);
         return dense_ws_layout(n, 2, p.blocks).total;
     }
+    case PERM_KIND_SPARSE_F64: {
+        const SweepPlan p = plan_sweep(n, 0);
+        return dense_ws_layout(n, 1, p.blocks).total + align256(size_t(n) * n * sizeof(double));
+    }
+    case PERM_KIND_BINARY: {
+        const SweepPlan p = plan_sweep(n, 0);
+        return binary_ws_layout(n, p.blocks).total;
+    }
     default: return 0;
     }
 }
@@ -127,18 +206,130 @@ int perm_dense_c128(int n, const perm_c128 *A, int64_t lda, perm_c128 *out, void
                              static_cast<hipStream_t>(stream));
 }
 
-int perm_sparse_f64(int, const int32_t *, const int32_t *, const double *, int32_t, double *,
-                    void *, size_t, void *)
+int perm_sparse_f64(int n, const int32_t *col_ptr, const int32_t *row_idx, const double *vals,
+                    int32_t nnz, double *out, void *ws, size_t ws_bytes, void *stream)
 {
-    return PERM_EUNSUPPORTED;
+    if (!valid_n(n) || !out) return PERM_EINVAL;
+    if (n > 0 && (!valid_csc(n, col_ptr, row_idx, nnz) || (nnz > 0 && !vals))) return PERM_EINVAL;
+    const int w = check_ws(ws, ws_bytes, perm_workspace_bytes(PERM_KIND_SPARSE_F64, n, nnz));
+    if (w != PERM_OK) return w;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char *base = static_cast<char *>(ws);
+    if (n == 0) return launch_dense_f64(0, nullptr, 0, out, base, st);
+    // Stage the matrix row-major behind the dense workspace; the sweep then
+    // updates x with whole columns held in scalar registers (zeros included).
+    const SweepPlan p = plan_sweep(n, 0);
+    const size_t off = dense_ws_layout(n, 1, p.blocks).total;
+    std::vector<double> dense(size_t(n) * n, 0.0);
+    for (int j = 0; j < n; ++j)
+        for (int32_t q = col_ptr[j]; q < col_ptr[j + 1]; ++q) dense[size_t(row_idx[q]) * n + j] = vals[q];
+    if (hipMemcpyAsync(base + off, dense.data(), dense.size() * sizeof(double),
+                       hipMemcpyHostToDevice, st) != hipSuccess)
+        return PERM_EHIP;
+    // the host staging buffer must outlive the copy
+    if (hipStreamSynchronize(st) != hipSuccess) return PERM_EHIP;
+    return launch_dense_f64(n, reinterpret_cast<const double *>(base + off), n, out, base, st);
 }
 
-int perm_binary_exact(int, const int32_t *, const int32_t *, int32_t, int, uint64_t *, uint64_t *,
-                      void *, size_t, void *)
+int perm_binary_exact(int n, const int32_t *col_ptr, const int32_t *row_idx, int32_t nnz,
+                      int n_primes, uint64_t out_limbs[5], uint64_t *out_residues,
+                      int *out_nprimes, void *ws, size_t ws_bytes, void *stream)
 {
-    return PERM_EUNSUPPORTED;
+    if (!valid_n(n) || !out_limbs || n_primes < 0 || n_primes > kMaxPrimes) return PERM_EINVAL;
+    if (n > 0 && !valid_csc(n, col_ptr, row_idx, nnz)) return PERM_EINVAL;
+    for (int k = 0; k < 5; ++k) out_limbs[k] = 0;
+    if (out_residues)
+        for (int k = 0; k < kMaxPrimes; ++k) out_residues[k] = 0;
+    if (n == 0) {
+        const int np0 = n_primes ? n_primes : 3;
+        out_limbs[0] = 1;
+        if (out_residues)
+            for (int k = 0; k < np0; ++k) out_residues[k] = 1;
+        if (out_nprimes) *out_nprimes = np0;
+        return PERM_OK;
+    }
+    // Dense 0/1 pattern, row sums, and the number of primes from the bound.
+    std::vector<double> dense(size_t(n) * n, 0.0);
+    std::vector<int> rsum(n, 0), csum(n, 0);
+    for (int j = 0; j < n; ++j)
+        for (int32_t p = col_ptr[j]; p < col_ptr[j + 1]; ++p) {
+            dense[size_t(row_idx[p]) * n + j] = 1.0;
+            rsum[row_idx[p]]++;
+            csum[j]++;
+        }
+    bool empty_line = false;
+    for (int i = 0; i < n; ++i) empty_line = empty_line || rsum[i] == 0 || csum[i] == 0;
+    int needed = 3;
+    if (!empty_line) {
+        const double bits = bregman_log2(rsum) + 1.0;  // +1: margin for rounding of the bound
+        while (needed < kMaxPrimes && double(needed) * 60.99 < bits) ++needed;
+        if (double(needed) * 60.99 < bits) return PERM_ERANGE;
+    }
+    const int np = n_primes == 0 ? needed : n_primes;
+    if (np < needed && !empty_line) return PERM_ERANGE;
+    if (out_nprimes) *out_nprimes = np;
+    if (empty_line) return PERM_OK;  // an empty row or column: no perfect matching
+    const SweepPlan plan = plan_sweep(n, 0);
+    const BinaryWs L = binary_ws_layout(n, plan.blocks);
+    const int w = check_ws(ws, ws_bytes, L.total);
+    if (w != PERM_OK) return w;
+
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char *base = static_cast<char *>(ws);
+    if (hipMemcpyAsync(base + L.dense01, dense.data(), dense.size() * sizeof(double),
+                       hipMemcpyHostToDevice, st) != hipSuccess)
+        return PERM_EHIP;
+    uint64_t *res_dev = reinterpret_cast<uint64_t *>(base + L.residues);
+    const int rc = launch_binary_residues(n, reinterpret_cast<const double *>(base + L.dense01),
+                                          np, res_dev, base, st);
+    if (rc != PERM_OK) return rc;
+    uint64_t R[kMaxPrimes] = {0, 0, 0, 0, 0};
+    if (hipMemcpyAsync(R, res_dev, sizeof(uint64_t) * np, hipMemcpyDeviceToHost, st) != hipSuccess)
+        return PERM_EHIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return PERM_EHIP;
+
+    // R_k = (-1)^(n-1) 2^(n-1) perm  (mod p_k)
+    uint64_t res[kMaxPrimes];
+    for (int k = 0; k < np; ++k) {
+        const uint64_t p = host_prime(k);
+        const uint64_t inv2 = (p + 1) / 2;
+        uint64_t v = mulmod_host(R[k] % p, powmod_host(inv2, uint64_t(n - 1), p), p);
+        if (!(n & 1) && v) v = p - v;
+        res[k] = v;
+        if (out_residues) out_residues[k] = v;
+    }
+    // Garner: perm = t_0 + p_0 (t_1 + p_1 (t_2 + ...)), 0 <= perm < prod p_k.
+    uint64_t t[kMaxPrimes];
+    for (int k = 0; k < np; ++k) {
+        const uint64_t pk = host_prime(k);
+        uint64_t v = res[k];
+        for (int j = 0; j < k; ++j) {
+            const uint64_t pj = host_prime(j) % pk;
+            const uint64_t inv = powmod_host(pj, pk - 2, pk);
+            v = mulmod_host((v + pk - t[j] % pk) % pk, inv, pk);
+        }
+        t[k] = v;
+    }
+    uint64_t limbs[6] = {0, 0, 0, 0, 0, 0};
+    limbs[0] = t[np - 1];
+    for (int k = np - 2; k >= 0; --k) {
+        // limbs = limbs * p_k + t_k
+        unsigned __int128 carry = t[k];
+        const uint64_t pk = host_prime(k);
+        for (int q = 0; q < 6; ++q) {
+            const unsigned __int128 v = (unsigned __int128)limbs[q] * pk + carry;
+            limbs[q] = uint64_t(v);
+            carry = v >> 64;
+        }
+    }
+    for (int q = 0; q < 5; ++q) out_limbs[q] = limbs[q];
+    return PERM_OK;
 }
 
-uint64_t perm_binary_prime(int) { return 0; }
+uint64_t perm_binary_prime(int k)
+{
+    if (k < 0 || k >= kMaxPrimes) return 0;
+    return host_prime(k);
+}
 
 }  // extern "C"

@@ -16,7 +16,7 @@ namespace perm {
 constexpr int kBlock = 256;          // threads per block: 4 waves of 64
 constexpr int kWave = 64;
 constexpr int kWavesPerBlock = kBlock / kWave;
-constexpr int kSerialMaxN = 8;       // n <= 8: 2^(n-1) <= 128 steps, one lane
+constexpr int kMaxPrimes = 5;        // binary path: at most 5 primes of 61 bits
 
 // Gray-walk decomposition of the 2^(n-1) steps of one matrix:
 //   lanes * 2^log2_chunk == 2^(n-1), every lane walks one contiguous chunk,
@@ -77,6 +77,18 @@ struct DenseWs {
 
 DenseWs dense_ws_layout(int n, int components, int64_t blocks);
 
+struct BinaryWs {
+    size_t dense01 = 0;   // n*n doubles, the 0/1 pattern row-major (staged from the host CSC)
+    size_t ycol = 0;      // n*n doubles, 2 a_ij column-major
+    size_t yneg = 0;      // n*n doubles, -2 a_ij
+    size_t y0 = 0;        // n doubles, 2 a_{i,n-1} - r_i
+    size_t partials = 0;  // blocks * kMaxPrimes uint64 residues
+    size_t residues = 0;  // kMaxPrimes uint64 residues of the whole sum
+    size_t total = 0;
+};
+
+BinaryWs binary_ws_layout(int n, int64_t blocks);
+
 // ---------------------------------------------------------------------------
 // Kernel launchers (defined in the .hip files).  All return PERM_OK or
 // PERM_EHIP and only enqueue work on `stream`.
@@ -85,5 +97,8 @@ int launch_dense_f64(int n, const double *A, int64_t lda, double *out, char *ws,
                      hipStream_t stream);
 int launch_dense_c128(int n, const perm_c128 *A, int64_t lda, perm_c128 *out, char *ws,
                       hipStream_t stream);
+// Residues R_k = sum_g (-1)^g prod_i y_i(g) mod p_k (k < nprimes) into residues_dev.
+int launch_binary_residues(int n, const double *dense01, int nprimes, uint64_t *residues_dev,
+                           char *ws, hipStream_t stream);
 
 }  // namespace perm

@@ -62,3 +62,70 @@ def test_dense_argument_errors(fn):
     assert f(4, FAKE, 4, None, FAKE, ws_big, None) == N.PERM_EINVAL
     assert f(20, FAKE, 20, FAKE, None, ws_big, None) == N.PERM_EWORKSPACE
     assert f(20, FAKE, 20, FAKE, FAKE, 16, None) == N.PERM_EWORKSPACE
+
+
+def test_binary_argument_errors():
+    import numpy as np
+    lib = N.lib()
+    limbs = np.zeros(5, np.uint64)
+    cp = np.array([0, 1, 2], np.int32)
+    ri = np.array([0, 1], np.int32)
+    big = 1 << 30
+    f = lib.perm_binary_exact
+    assert f(-1, cp.ctypes.data, ri.ctypes.data, 2, 0, limbs.ctypes.data, None, None, FAKE, big, None) == N.PERM_EINVAL
+    assert f(2, cp.ctypes.data, ri.ctypes.data, 2, 0, None, None, None, FAKE, big, None) == N.PERM_EINVAL
+    assert f(2, cp.ctypes.data, ri.ctypes.data, 2, 6, limbs.ctypes.data, None, None, FAKE, big, None) == N.PERM_EINVAL
+    bad_ptr = np.array([0, 2, 1], np.int32)      # not monotone / wrong end
+    assert f(2, bad_ptr.ctypes.data, ri.ctypes.data, 2, 0, limbs.ctypes.data, None, None, FAKE, big, None) == N.PERM_EINVAL
+    bad_rows = np.array([1, 0], np.int32)
+    cp1 = np.array([0, 2, 2], np.int32)          # column 0 holds rows 1, 0: unsorted
+    assert f(2, cp1.ctypes.data, bad_rows.ctypes.data, 2, 0, limbs.ctypes.data, None, None, FAKE, big, None) == N.PERM_EINVAL
+    oob = np.array([0, 5], np.int32)
+    assert f(2, cp.ctypes.data, oob.ctypes.data, 2, 0, limbs.ctypes.data, None, None, FAKE, big, None) == N.PERM_EINVAL
+    # a full 2x2 pattern needs the workspace
+    cpf = np.array([0, 2, 4], np.int32)
+    rif = np.array([0, 1, 0, 1], np.int32)
+    assert f(2, cpf.ctypes.data, rif.ctypes.data, 4, 0, limbs.ctypes.data, None, None, None, 0, None) == N.PERM_EWORKSPACE
+    # too few primes for the bound of J_32 (32! > 2^117) -> ERANGE before any GPU work
+    n = 32
+    cpj = np.arange(0, n * n + 1, n, dtype=np.int32)
+    rij = np.tile(np.arange(n, dtype=np.int32), n)
+    assert f(n, cpj.ctypes.data, rij.ctypes.data, n * n, 1, limbs.ctypes.data, None, None, FAKE, big, None) == N.PERM_ERANGE
+
+
+def test_binary_primes_are_primes_below_2_61():
+    def is_prime(m):
+        d, s = m - 1, 0
+        while d % 2 == 0:
+            d //= 2
+            s += 1
+        for a in (2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37):
+            x = pow(a, d, m)
+            if x in (1, m - 1):
+                continue
+            for _ in range(s - 1):
+                x = x * x % m
+                if x == m - 1:
+                    break
+            else:
+                return False
+        return True
+    lib = N.lib()
+    ps = [lib.perm_binary_prime(k) for k in range(5)]
+    assert len(set(ps)) == 5 and all(2 ** 60 < p < 2 ** 61 and is_prime(p) for p in ps)
+    assert lib.perm_binary_prime(5) == 0
+
+
+def test_sparse_argument_errors():
+    import numpy as np
+    lib = N.lib()
+    f = lib.perm_sparse_f64
+    cp = np.array([0, 1, 2], np.int32)
+    ri = np.array([0, 1], np.int32)
+    v = np.array([1.0, 2.0])
+    big = 1 << 30
+    assert f(-1, cp.ctypes.data, ri.ctypes.data, v.ctypes.data, 2, FAKE, FAKE, big, None) == N.PERM_EINVAL
+    assert f(2, cp.ctypes.data, ri.ctypes.data, None, 2, FAKE, FAKE, big, None) == N.PERM_EINVAL
+    assert f(2, cp.ctypes.data, ri.ctypes.data, v.ctypes.data, 3, FAKE, FAKE, big, None) == N.PERM_EINVAL
+    assert f(2, cp.ctypes.data, ri.ctypes.data, v.ctypes.data, 2, None, FAKE, big, None) == N.PERM_EINVAL
+    assert f(2, cp.ctypes.data, ri.ctypes.data, v.ctypes.data, 2, FAKE, None, 0, None) == N.PERM_EWORKSPACE

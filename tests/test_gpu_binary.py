@@ -1,0 +1,95 @@
+"""Bit-exact parity of the binary (modular + CRT) HIP path with the oracle."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2502_16577_amd import api
+from paper_2502_16577_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "full_size.json")
+
+
+def derangements(n):
+    d = [1, 0]
+    for k in range(2, n + 1):
+        d.append((k - 1) * (d[k - 1] + d[k - 2]))
+    return d[n]
+
+
+def fib(n):
+    a, b = 0, 1
+    for _ in range(n):
+        a, b = b, a + b
+    return a
+
+
+def check_residues(value, residues):
+    for k, r in enumerate(residues):
+        assert r == value % api.binary_prime(k), k
+
+
+@pytest.mark.parametrize("n", list(range(1, 25)))
+def test_bernoulli_small(oracle, n):
+    a = W.bernoulli(n, 800 + n)
+    got, res = api.perm_binary_exact(a)
+    assert got == oracle.binary(a), n
+    check_residues(got, res)
+
+
+@pytest.mark.parametrize("n,per_row", [(14, 3), (18, 4), (22, 5), (26, 6)])
+def test_sparse_rows_small(oracle, n, per_row):
+    a = W.sparse_rows(n, per_row, 900 + n)
+    got, res = api.perm_binary_exact(a)
+    assert got == oracle.binary(a)
+    check_residues(got, res)
+
+
+@pytest.mark.parametrize("n", [13, 20, 27, 34])
+def test_closed_forms(n):
+    assert api.perm_binary_exact(np.ones((n, n), np.uint8))[0] == math.factorial(n)
+    assert api.perm_binary_exact(W.ones_minus_identity(n).astype(np.uint8))[0] == derangements(n)
+    assert api.perm_binary_exact(W.tridiagonal_ones(n).astype(np.uint8))[0] == fib(n + 1)
+
+
+def test_more_primes_than_needed_agree():
+    a = W.bernoulli(20, 5)
+    v3, r3 = api.perm_binary_exact(a, n_primes=3)
+    v5, r5 = api.perm_binary_exact(a, n_primes=5)
+    assert v3 == v5 and r3 == r5[:3]
+    check_residues(v5, r5)
+
+
+def test_empty_row_gives_zero():
+    a = W.bernoulli(16, 2)
+    a[3, :] = 0
+    assert api.perm_binary_exact(a)[0] == 0
+
+
+def _golden(name):
+    with open(GOLDEN) as f:
+        data = json.load(f)
+    if name not in data:
+        pytest.skip(f"no stored oracle value for {name}: run tests/golden/make_golden.py {name}")
+    return data[name]
+
+
+def test_full_size_bernoulli32():
+    g = _golden("bernoulli32")
+    a = W.bernoulli(32, W.SEED_BERNOULLI32)
+    assert W.digest(a) == g["digest"]
+    got, res = api.perm_binary_exact(a)
+    assert got == int(g["value"])
+    check_residues(got, res)
+
+
+def test_full_size_sparse40():
+    g = _golden("sparse40")
+    a = W.sparse_rows(40, 6, W.SEED_SPARSE40)
+    assert W.digest(a) == g["digest"]
+    got, res = api.perm_binary_exact(a)
+    assert got == int(g["value"])
+    check_residues(got, res)
