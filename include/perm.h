@@ -136,6 +136,78 @@ int perm_binary_exact(int n, const int32_t *col_ptr, const int32_t *row_idx,
                       uint64_t *out_residues, int *out_nprimes, void *ws,
                       size_t ws_bytes, void *stream);
 
+/* Element types for perm_grad. */
+#define PERM_DTYPE_F64  1
+#define PERM_DTYPE_C128 2
+
+/*
+ * Permanent and its gradient G_ij = dperm/da_ij in the same sweep.  The
+ * permanent is multilinear in the entries, and with tau_j(g) = +1 if column
+ * j is in the Gray subset S_g or j = n-1, else -1, differentiating the sum of
+ * Algorithm 1 term by term gives G = (-1)^(n-1) sum_g (-1)^g L(g) tau(g)^T,
+ * L_i(g) = prod_{k != i} x_k(g).  L comes from prefix / suffix products (no
+ * division); the rank-1 updates of 64 subsets at a time are one FP64 MFMA
+ * contraction.  For complex A, G is the complex (holomorphic) derivative.
+ *   dtype     PERM_DTYPE_F64 (A, out_perm, out_grad are double) or
+ *             PERM_DTYPE_C128 (perm_c128)
+ *   A         device, row-major, lda >= n
+ *   out_perm  device, one element
+ *   out_grad  device, n x n row-major elements
+ * n <= 32 (PERM_EUNSUPPORTED above).
+ */
+int perm_grad(int n, int dtype, const void *A, int64_t lda, void *out_perm,
+              void *out_grad, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Batched permanents (and gradients) of many small complex matrices of uneven
+ * order, e.g. the amplitudes of photon-counting distributions (Section 1):
+ * one persistent launch in which waves pull (matrix, chunk) work items,
+ * largest orders first, and per-item partials are summed per matrix in a
+ * fixed order.
+ *
+ * A plan holds the work list and launch shapes for one set of orders; it is
+ * host memory owned by the caller (create / destroy), not thread-safe, and
+ * caches the hipGraph of the launch for the last (data, out, grad, ws).
+ *   count      number of matrices (>= 1)
+ *   k          host int32[count], orders 1..32
+ *   offset     host int64[count], element offset of matrix m in `data`
+ *              (row-major k x k perm_c128; the same packing is used for grad)
+ *   want_grad  nonzero: also compute dperm/dA of every matrix
+ */
+typedef struct perm_plan perm_plan;
+
+int perm_batched_plan_create(int count, const int32_t *k, const int64_t *offset,
+                             int want_grad, perm_plan **plan);
+void perm_plan_destroy(perm_plan *plan);
+
+/* Device workspace bytes for any launch (and any autotuning) of this plan. */
+size_t perm_batched_workspace_bytes(const perm_plan *plan);
+
+/*
+ * Runs the batch.  data, out (perm_c128[count]) and grad (same packing as
+ * data; required if the plan wants gradients) are device pointers.  The plan
+ * is copied into `ws` on first use with this ws (a synchronous copy); with
+ * use_graph != 0 the launch is captured once into a hipGraph (reset, staging,
+ * persistent kernels on forked streams, finalize) and replayed with
+ * hipGraphLaunch on `stream`.
+ */
+int perm_batched(perm_plan *plan, const perm_c128 *data, perm_c128 *out, perm_c128 *grad,
+                 int use_graph, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Autotuner: times the batch for every candidate of (steps per lane,
+ * persistent grid size) on this device and keeps the fastest in the plan.
+ * Synchronises `stream`; writes the outputs as a side effect.  best_ms
+ * (nullable) receives the time of the chosen configuration.
+ */
+int perm_batched_autotune(perm_plan *plan, const perm_c128 *data, perm_c128 *out,
+                          perm_c128 *grad, void *ws, size_t ws_bytes, void *stream,
+                          double *best_ms);
+
+/* Plan introspection: number of work items, chosen log2 steps per lane, grid. */
+int perm_batched_plan_info(const perm_plan *plan, int64_t *n_items, int *log2_chunk,
+                           int64_t *grid_small);
+
 /* The k-th prime used by perm_binary_exact (k = 0..4), 0 if out of range. */
 uint64_t perm_binary_prime(int k);
 

@@ -43,6 +43,13 @@ SIGNATURES = [
     ("perm_sparse_f64", _int, [_int, _vp, _vp, _vp, _i32, _vp, _vp, _sz, _vp]),
     ("perm_binary_exact", _int, [_int, _vp, _vp, _i32, _int, _vp, _vp, _vp, _vp, _sz, _vp]),
     ("perm_binary_prime", _u64, [_int]),
+    ("perm_grad", _int, [_int, _int, _vp, _i64, _vp, _vp, _vp, _sz, _vp]),
+    ("perm_batched_plan_create", _int, [_int, _vp, _vp, _int, ctypes.POINTER(_vp)]),
+    ("perm_plan_destroy", None, [_vp]),
+    ("perm_batched_workspace_bytes", _sz, [_vp]),
+    ("perm_batched", _int, [_vp, _vp, _vp, _vp, _int, _vp, _sz, _vp]),
+    ("perm_batched_autotune", _int, [_vp, _vp, _vp, _vp, _vp, _sz, _vp, ctypes.POINTER(ctypes.c_double)]),
+    ("perm_batched_plan_info", _int, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_int), ctypes.POINTER(_i64)]),
 ]
 
 _lock = threading.Lock()

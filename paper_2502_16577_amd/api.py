@@ -143,3 +143,120 @@ def perm_binary_exact(a01=None, *, csc=None, n_primes: int = 0, device="cuda:0",
 
 def binary_prime(k: int) -> int:
     return int(N.lib().perm_binary_prime(k))
+
+
+DTYPE_F64 = 1
+DTYPE_C128 = 2
+
+
+def perm_grad(A: torch.Tensor, out_perm=None, out_grad=None, ws=None):
+    """Permanent and dperm/dA of a dense float64 / complex128 CUDA matrix (n <= 32).
+
+    Returns (perm as a 0-d tensor, G as an n x n tensor); for complex A, G is
+    the complex derivative dperm/da_ij."""
+    _check_square(A)
+    if A.dtype == torch.float64:
+        dt, kind = DTYPE_F64, N.KIND_GRAD_F64
+    elif A.dtype == torch.complex128:
+        dt, kind = DTYPE_C128, N.KIND_GRAD_C128
+    else:
+        raise TypeError("float64 or complex128 expected")
+    n = A.shape[0]
+    if out_perm is None:
+        out_perm = torch.empty((), dtype=A.dtype, device=A.device)
+    if out_grad is None:
+        out_grad = torch.empty((n, n), dtype=A.dtype, device=A.device)
+    ws, need = _workspace(kind, n, 0, A.device, ws)
+    st = N.lib().perm_grad(n, dt, A.data_ptr() if n else None, A.stride(0) if n else 0,
+                           out_perm.data_ptr(), out_grad.data_ptr() if n else None,
+                           ws.data_ptr(), need, _stream(A.device))
+    N.check(st, "perm_grad")
+    return out_perm, out_grad
+
+
+class Perm(torch.autograd.Function):
+    """perm(A) with a hand-written adjoint: forward runs perm_grad when A
+    needs a gradient (the gradient comes from the same sweep), backward
+    returns grad_out * G (real) or grad_out * conj(G) (complex, PyTorch's
+    convention for holomorphic functions)."""
+
+    @staticmethod
+    def forward(ctx, A):
+        if ctx.needs_input_grad[0]:
+            p, g = perm_grad(A)
+            ctx.save_for_backward(g)
+            return p
+        return perm(A)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (g,) = ctx.saved_tensors
+        if g.is_complex():
+            return grad_out * g.conj()
+        return grad_out * g
+
+
+def permanent(A: torch.Tensor) -> torch.Tensor:
+    """Differentiable permanent of a dense float64 / complex128 CUDA matrix."""
+    return Perm.apply(A)
+
+
+class BatchedPlan:
+    """Plan of a batched permanent (+ gradient) launch over packed complex matrices.
+
+    ``ks``: orders (1..32); ``offsets``: element offsets into the packed data
+    (``workloads.pack`` produces both).  Owns the C plan and a workspace."""
+
+    def __init__(self, ks, offsets, want_grad: bool = True, device="cuda:0"):
+        self.ks = np.ascontiguousarray(ks, dtype=np.int32)
+        self.offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+        self.count = int(self.ks.size)
+        self.want_grad = bool(want_grad)
+        self.device = torch.device(device)
+        h = ctypes.c_void_p()
+        N.check(N.lib().perm_batched_plan_create(self.count, self.ks.ctypes.data,
+                                                 self.offsets.ctypes.data, int(want_grad),
+                                                 ctypes.byref(h)), "perm_batched_plan_create")
+        self._h = h
+        nb = int(N.lib().perm_batched_workspace_bytes(h))
+        self.ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=self.device)
+        self.ws_bytes = nb
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            N.lib().perm_plan_destroy(h)
+            self._h = None
+
+    def outputs(self, data: torch.Tensor):
+        out = torch.empty(self.count, dtype=torch.complex128, device=self.device)
+        grad = torch.empty_like(data) if self.want_grad else None
+        return out, grad
+
+    def run(self, data: torch.Tensor, out=None, grad=None, use_graph: bool = True):
+        if data.dtype != torch.complex128 or data.device != self.device or not data.is_contiguous():
+            raise ValueError("contiguous complex128 data on the plan's device expected")
+        if out is None:
+            out, g2 = self.outputs(data)
+            grad = g2 if grad is None else grad
+        st = N.lib().perm_batched(self._h, data.data_ptr(), out.data_ptr(),
+                                  grad.data_ptr() if grad is not None else None, int(use_graph),
+                                  self.ws.data_ptr(), self.ws_bytes, _stream(self.device))
+        N.check(st, "perm_batched")
+        return out, grad
+
+    def autotune(self, data: torch.Tensor):
+        out, grad = self.outputs(data)
+        best = ctypes.c_double(0.0)
+        N.check(N.lib().perm_batched_autotune(self._h, data.data_ptr(), out.data_ptr(),
+                                              grad.data_ptr() if grad is not None else None,
+                                              self.ws.data_ptr(), self.ws_bytes,
+                                              _stream(self.device), ctypes.byref(best)),
+                "perm_batched_autotune")
+        return best.value
+
+    def info(self):
+        ni, lc, gs = ctypes.c_int64(), ctypes.c_int(), ctypes.c_int64()
+        N.check(N.lib().perm_batched_plan_info(self._h, ctypes.byref(ni), ctypes.byref(lc),
+                                               ctypes.byref(gs)), "perm_batched_plan_info")
+        return {"items": ni.value, "log2_chunk": lc.value, "grid_small": gs.value}

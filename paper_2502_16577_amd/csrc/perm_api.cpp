@@ -77,6 +77,27 @@ BinaryWs binary_ws_layout(int n, int64_t blocks)
     return L;
 }
 
+GradWs grad_ws_layout(int n, int components, int64_t waves)
+{
+    GradWs L;
+    size_t off = 0;
+    const size_t nn = size_t(n) * size_t(n) * size_t(components) * sizeof(double);
+    L.acol = off;
+    off += align256(nn);
+    L.aneg = off;
+    off += align256(nn);
+    L.x0 = off;
+    off += align256(size_t(n) * size_t(components) * sizeof(double));
+    L.perm_partials = off;
+    off += align256(size_t(std::max<int64_t>(waves, 1)) * 2 * sizeof(dd));
+    L.grad_partials = off;
+    const size_t tiles = size_t((n + 15) / 16) * size_t((n + 15) / 16);
+    off += align256(size_t(std::max<int64_t>(waves, 1)) * size_t(components) * tiles * 4 * kWave *
+                    sizeof(dd));
+    L.total = off;
+    return L;
+}
+
 // Host copy of the primes 2^61 - c used by the binary kernels.
 constexpr uint64_t kPrimeCHost[kMaxPrimes] = {1, 31, 45, 229, 259};
 
@@ -175,6 +196,12 @@ size_t perm_workspace_bytes(int kind, int n, int64_t m)
     case PERM_KIND_SPARSE_F64: {
         const SweepPlan p = plan_sweep(n, 0);
         return dense_ws_layout(n, 1, p.blocks).total + align256(size_t(n) * n * sizeof(double));
+    }
+    case PERM_KIND_GRAD_F64:
+    case PERM_KIND_GRAD_C128: {
+        if (n > kGradMaxN) return 0;
+        const GradPlan p = plan_grad(n);
+        return grad_ws_layout(n, kind == PERM_KIND_GRAD_C128 ? 2 : 1, p.waves).total;
     }
     case PERM_KIND_BINARY: {
         const SweepPlan p = plan_sweep(n, 0);
@@ -324,6 +351,24 @@ int perm_binary_exact(int n, const int32_t *col_ptr, const int32_t *row_idx, int
     }
     for (int q = 0; q < 5; ++q) out_limbs[q] = limbs[q];
     return PERM_OK;
+}
+
+int perm_grad(int n, int dtype, const void *A, int64_t lda, void *out_perm, void *out_grad,
+              void *ws, size_t ws_bytes, void *stream)
+{
+    if (!valid_n(n) || !out_perm || (n > 0 && (!out_grad || !A || lda < n))) return PERM_EINVAL;
+    if (dtype != PERM_DTYPE_F64 && dtype != PERM_DTYPE_C128) return PERM_EINVAL;
+    if (n > kGradMaxN) return PERM_EUNSUPPORTED;
+    const bool cplx = dtype == PERM_DTYPE_C128;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (n == 0) {
+        return cplx ? launch_dense_c128(0, nullptr, 0, static_cast<perm_c128 *>(out_perm), nullptr, st)
+                    : launch_dense_f64(0, nullptr, 0, static_cast<double *>(out_perm), nullptr, st);
+    }
+    const int kind = cplx ? PERM_KIND_GRAD_C128 : PERM_KIND_GRAD_F64;
+    const int w = check_ws(ws, ws_bytes, perm_workspace_bytes(kind, n, 0));
+    if (w != PERM_OK) return w;
+    return launch_grad(n, cplx, A, lda, out_perm, out_grad, static_cast<char *>(ws), st);
 }
 
 uint64_t perm_binary_prime(int k)

@@ -1,0 +1,323 @@
+// Host side of the batched entry points: the plan (work list, workspace
+// layout, launch shapes), its autotuner, the upload of the plan into the
+// caller's workspace and the hipGraph that replays one batched launch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "batched_internal.h"
+#include "perm.h"
+
+using namespace perm;
+
+namespace {
+
+// Tuning knobs.  log2_chunk is the number of Gray steps per lane (log2) used
+// for large matrices; the grids are persistent one-wave blocks per group.
+struct BatchTuning {
+    int log2_chunk = 10;
+    int64_t grid[kBatchGroups] = {2048, 1024, 1024};
+};
+
+// Candidates the autotuner times.
+const int kTuneChunks[] = {8, 10, 12};
+const int64_t kTuneGridSmall[] = {1024, 2048};
+
+}  // namespace
+
+struct perm_plan {
+    int count = 0;
+    int want_grad = 0;
+    std::vector<int32_t> k;
+    std::vector<int64_t> off;
+    BatchTuning tune;
+    // derived from (k, tune)
+    std::vector<BatchMatDev> mats;
+    std::vector<BatchItemDev> items[kBatchGroups];
+    int64_t n_items_total = 0;
+    int64_t stage_doubles = 0;
+    int64_t g_dd = 0;
+    // workspace layout (bytes)
+    size_t o_mats = 0, o_items[kBatchGroups] = {0, 0, 0}, o_counters = 0, o_stage = 0, o_perm = 0,
+           o_grad = 0, total = 0;
+    size_t ws_max = 0;  // over every tuning candidate
+    // caches
+    const void *uploaded_ws = nullptr;
+    hipGraphExec_t exec = nullptr;
+    const void *g_data = nullptr, *g_out = nullptr, *g_grad = nullptr, *g_ws = nullptr;
+    hipStream_t side[kBatchGroups] = {nullptr, nullptr, nullptr};
+    hipStream_t capture = nullptr;
+    hipEvent_t fork = nullptr, join[kBatchGroups] = {nullptr, nullptr, nullptr};
+};
+
+namespace {
+
+size_t a256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Per-matrix walk decomposition: at most 2^log2_chunk steps per lane, whole
+// 64-lane waves where the matrix has enough steps (2^(k-1) >= 128), and
+// r <= c - 1 so the lane-dependent flip at 2^(c-1) is an exact re-seed.
+void derive(perm_plan &P)
+{
+    const int ct = P.tune.log2_chunk;
+    P.mats.assign(P.count, BatchMatDev{});
+    for (int g = 0; g < kBatchGroups; ++g) P.items[g].clear();
+    int64_t item0 = 0, stage = 0, gdd = 0;
+    for (int m = 0; m < P.count; ++m) {
+        BatchMatDev &M = P.mats[m];
+        const int k = P.k[m];
+        M.k = k;
+        M.data_off = P.off[m];
+        if (k == 1) {
+            M.c = 0;
+            M.r = 0;
+            M.waves = 1;
+        } else {
+            const int total = k - 1;
+            const int c = std::max(1, std::min(ct, total - 6));
+            M.c = c;
+            M.r = std::min(9, c - 1);
+            const int64_t lanes = int64_t(1) << (total - c);
+            M.waves = int32_t(std::max<int64_t>(1, lanes / kWave));
+        }
+        M.stage = stage;
+        stage += 4 * int64_t(k) * k + 2 * int64_t(k);
+        M.item0 = item0;
+        item0 += M.waves;
+        M.gbase = gdd;
+        if (P.want_grad) gdd += int64_t(M.waves) * 2 * k * k;
+    }
+    // Work list per group: largest order first (longest items first), then
+    // matrix, then wave -- a fixed order, so the plan is deterministic.
+    std::vector<int> order(P.count);
+    for (int m = 0; m < P.count; ++m) order[m] = m;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return P.k[a] > P.k[b]; });
+    for (int m : order) {
+        const int g = batch_group(P.k[m]);
+        for (int w = 0; w < P.mats[m].waves; ++w) P.items[g].push_back(BatchItemDev{m, w});
+    }
+    P.n_items_total = item0;
+    P.stage_doubles = stage;
+    P.g_dd = gdd;
+    size_t o = 0;
+    P.o_mats = o;
+    o += a256(sizeof(BatchMatDev) * size_t(P.count));
+    for (int g = 0; g < kBatchGroups; ++g) {
+        P.o_items[g] = o;
+        o += a256(sizeof(BatchItemDev) * std::max<size_t>(1, P.items[g].size()));
+    }
+    P.o_counters = o;
+    o += a256(sizeof(uint32_t) * kBatchGroups);
+    P.o_stage = o;
+    o += a256(sizeof(double) * size_t(stage));
+    P.o_perm = o;
+    o += a256(sizeof(dd) * 2 * size_t(item0));
+    P.o_grad = o;
+    o += a256(sizeof(dd) * size_t(std::max<int64_t>(gdd, 1)));
+    P.total = o;
+}
+
+void drop_graph(perm_plan &P)
+{
+    if (P.exec) hipGraphExecDestroy(P.exec);
+    P.exec = nullptr;
+    P.g_data = P.g_out = P.g_grad = P.g_ws = nullptr;
+}
+
+int upload(perm_plan &P, char *ws, hipStream_t st)
+{
+    if (P.uploaded_ws == ws) return PERM_OK;
+    if (hipMemcpyAsync(ws + P.o_mats, P.mats.data(), sizeof(BatchMatDev) * P.mats.size(),
+                       hipMemcpyHostToDevice, st) != hipSuccess)
+        return PERM_EHIP;
+    for (int g = 0; g < kBatchGroups; ++g)
+        if (!P.items[g].empty() &&
+            hipMemcpyAsync(ws + P.o_items[g], P.items[g].data(),
+                           sizeof(BatchItemDev) * P.items[g].size(), hipMemcpyHostToDevice,
+                           st) != hipSuccess)
+            return PERM_EHIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return PERM_EHIP;
+    P.uploaded_ws = ws;
+    return PERM_OK;
+}
+
+BatchLaunch make_launch(const perm_plan &P, char *ws, const perm_c128 *data, perm_c128 *out,
+                        perm_c128 *grad)
+{
+    BatchLaunch L;
+    L.count = P.count;
+    L.mats = reinterpret_cast<const BatchMatDev *>(ws + P.o_mats);
+    for (int g = 0; g < kBatchGroups; ++g) {
+        L.items[g] = reinterpret_cast<const BatchItemDev *>(ws + P.o_items[g]);
+        L.n_items[g] = int64_t(P.items[g].size());
+        L.grid[g] = std::min<int64_t>(P.tune.grid[g], std::max<int64_t>(1, L.n_items[g]));
+    }
+    L.counters = reinterpret_cast<uint32_t *>(ws + P.o_counters);
+    L.stage = reinterpret_cast<double *>(ws + P.o_stage);
+    L.perm_parts = reinterpret_cast<dd *>(ws + P.o_perm);
+    L.g_parts = reinterpret_cast<dd *>(ws + P.o_grad);
+    L.data = data;
+    L.out = out;
+    L.grad = grad;
+    L.want_grad = P.want_grad;
+    return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+int perm_batched_plan_create(int count, const int32_t *k, const int64_t *offset, int want_grad,
+                             perm_plan **plan)
+{
+    if (!plan) return PERM_EINVAL;
+    *plan = nullptr;
+    if (count < 1 || !k || !offset) return PERM_EINVAL;
+    for (int m = 0; m < count; ++m)
+        if (k[m] < 1 || k[m] > kBatchMaxK || offset[m] < 0) return PERM_EINVAL;
+    perm_plan *P = new (std::nothrow) perm_plan;
+    if (!P) return PERM_EINVAL;
+    P->count = count;
+    P->want_grad = want_grad ? 1 : 0;
+    P->k.assign(k, k + count);
+    P->off.assign(offset, offset + count);
+    // the workspace must hold the largest layout over every tuning candidate
+    size_t mx = 0;
+    for (int ct : kTuneChunks) {
+        P->tune.log2_chunk = ct;
+        derive(*P);
+        mx = std::max(mx, P->total);
+    }
+    P->tune = BatchTuning{};
+    derive(*P);
+    P->ws_max = std::max(mx, P->total);
+    *plan = P;
+    return PERM_OK;
+}
+
+void perm_plan_destroy(perm_plan *plan)
+{
+    if (!plan) return;
+    drop_graph(*plan);
+    for (int g = 0; g < kBatchGroups; ++g) {
+        if (plan->side[g]) hipStreamDestroy(plan->side[g]);
+        if (plan->join[g]) hipEventDestroy(plan->join[g]);
+    }
+    if (plan->capture) hipStreamDestroy(plan->capture);
+    if (plan->fork) hipEventDestroy(plan->fork);
+    delete plan;
+}
+
+size_t perm_batched_workspace_bytes(const perm_plan *plan) { return plan ? plan->ws_max : 0; }
+
+int perm_batched(perm_plan *plan, const perm_c128 *data, perm_c128 *out, perm_c128 *grad,
+                 int use_graph, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!plan || !data || !out) return PERM_EINVAL;
+    if (plan->want_grad && !grad) return PERM_EINVAL;
+    if (!ws || ws_bytes < plan->ws_max) return PERM_EWORKSPACE;
+    perm_plan &P = *plan;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char *base = static_cast<char *>(ws);
+    int rc = upload(P, base, st);
+    if (rc != PERM_OK) return rc;
+    const BatchLaunch L = make_launch(P, base, data, out, grad);
+    if (!use_graph) return launch_batched(L, st);
+
+    if (!P.exec || P.g_data != data || P.g_out != out || P.g_grad != grad || P.g_ws != ws) {
+        drop_graph(P);
+        if (!P.capture && hipStreamCreateWithFlags(&P.capture, hipStreamNonBlocking) != hipSuccess)
+            return PERM_EHIP;
+        if (!P.fork && hipEventCreateWithFlags(&P.fork, hipEventDisableTiming) != hipSuccess)
+            return PERM_EHIP;
+        for (int g = 0; g < kBatchGroups; ++g) {
+            if (!P.side[g] && hipStreamCreateWithFlags(&P.side[g], hipStreamNonBlocking) != hipSuccess)
+                return PERM_EHIP;
+            if (!P.join[g] && hipEventCreateWithFlags(&P.join[g], hipEventDisableTiming) != hipSuccess)
+                return PERM_EHIP;
+        }
+        hipGraph_t graph = nullptr;
+        if (hipStreamBeginCapture(P.capture, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return PERM_EHIP;
+        rc = launch_batched_forked(L, P.capture, P.side, P.fork, P.join);
+        const hipError_t e = hipStreamEndCapture(P.capture, &graph);
+        if (rc != PERM_OK || e != hipSuccess || !graph) {
+            if (graph) hipGraphDestroy(graph);
+            return PERM_EHIP;
+        }
+        const hipError_t ie = hipGraphInstantiate(&P.exec, graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        if (ie != hipSuccess) {
+            P.exec = nullptr;
+            return PERM_EHIP;
+        }
+        P.g_data = data;
+        P.g_out = out;
+        P.g_grad = grad;
+        P.g_ws = ws;
+    }
+    return hipGraphLaunch(P.exec, st) == hipSuccess ? PERM_OK : PERM_EHIP;
+}
+
+int perm_batched_autotune(perm_plan *plan, const perm_c128 *data, perm_c128 *out,
+                          perm_c128 *grad, void *ws, size_t ws_bytes, void *stream,
+                          double *best_ms)
+{
+    if (!plan || !data || !out) return PERM_EINVAL;
+    if (plan->want_grad && !grad) return PERM_EINVAL;
+    if (!ws || ws_bytes < plan->ws_max) return PERM_EWORKSPACE;
+    perm_plan &P = *plan;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char *base = static_cast<char *>(ws);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return PERM_EHIP;
+    BatchTuning best = P.tune;
+    float best_t = 1e30f;
+    int rc = PERM_OK;
+    for (int ct : kTuneChunks) {
+        for (int64_t gs : kTuneGridSmall) {
+            P.tune.log2_chunk = ct;
+            P.tune.grid[0] = gs;
+            derive(P);
+            P.uploaded_ws = nullptr;
+            if ((rc = upload(P, base, st)) != PERM_OK) break;
+            const BatchLaunch L = make_launch(P, base, data, out, grad);
+            if ((rc = launch_batched(L, st)) != PERM_OK) break;  // warm-up
+            hipEventRecord(e0, st);
+            for (int rep = 0; rep < 2 && rc == PERM_OK; ++rep) rc = launch_batched(L, st);
+            hipEventRecord(e1, st);
+            if (hipEventSynchronize(e1) != hipSuccess) rc = PERM_EHIP;
+            if (rc != PERM_OK) break;
+            float ms = 0.f;
+            hipEventElapsedTime(&ms, e0, e1);
+            ms *= 0.5f;
+            if (ms < best_t) {
+                best_t = ms;
+                best = P.tune;
+            }
+        }
+        if (rc != PERM_OK) break;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    P.tune = best;
+    derive(P);
+    P.uploaded_ws = nullptr;
+    drop_graph(P);
+    if (best_ms) *best_ms = best_t;
+    return rc;
+}
+
+int perm_batched_plan_info(const perm_plan *plan, int64_t *n_items, int *log2_chunk,
+                           int64_t *grid_small)
+{
+    if (!plan) return PERM_EINVAL;
+    if (n_items) *n_items = plan->n_items_total;
+    if (log2_chunk) *log2_chunk = plan->tune.log2_chunk;
+    if (grid_small) *grid_small = plan->tune.grid[0];
+    return PERM_OK;
+}
+
+}  // extern "C"

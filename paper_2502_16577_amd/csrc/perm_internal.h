@@ -89,6 +89,28 @@ struct BinaryWs {
 
 BinaryWs binary_ws_layout(int n, int64_t blocks);
 
+// Gradient sweep: one wave per block, `waves` waves, lanes = 64 * waves.
+constexpr int kGradSerialMaxN = 10;  // n <= 10: one lane, direct formula
+constexpr int kGradMaxN = 32;        // MFMA tiles of G up to 2 x 2
+
+struct GradPlan {
+    int n = 0;
+    int log2_chunk = 0;
+    int log2_reseed = 0;
+    int64_t waves = 0;
+};
+
+GradPlan plan_grad(int n);
+
+struct GradWs {
+    size_t acol = 0, aneg = 0, x0 = 0;  // as DenseWs
+    size_t perm_partials = 0;           // waves * 2 dd
+    size_t grad_partials = 0;           // waves * components * tiles * 4 * 64 dd
+    size_t total = 0;
+};
+
+GradWs grad_ws_layout(int n, int components, int64_t waves);
+
 // ---------------------------------------------------------------------------
 // Kernel launchers (defined in the .hip files).  All return PERM_OK or
 // PERM_EHIP and only enqueue work on `stream`.
@@ -97,6 +119,9 @@ int launch_dense_f64(int n, const double *A, int64_t lda, double *out, char *ws,
                      hipStream_t stream);
 int launch_dense_c128(int n, const perm_c128 *A, int64_t lda, perm_c128 *out, char *ws,
                       hipStream_t stream);
+// Permanent and dperm/dA (row-major n x n, interleaved if complex).
+int launch_grad(int n, bool cplx, const void *A, int64_t lda, void *out_perm, void *out_grad,
+                char *ws, hipStream_t stream);
 // Residues R_k = sum_g (-1)^g prod_i y_i(g) mod p_k (k < nprimes) into residues_dev.
 int launch_binary_residues(int n, const double *dense01, int nprimes, uint64_t *residues_dev,
                            char *ws, hipStream_t stream);

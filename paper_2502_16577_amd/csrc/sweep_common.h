@@ -72,6 +72,14 @@ __device__ inline void acc_add(double &s, double &e, double v)
     e += err;
 }
 
+// Staging kernels (sweep_f64.hip, sweep_c128.hip): column-major +-A and x0.
+__global__ void prep_dense_f64(int n, const double *__restrict__ A, int64_t lda,
+                               double *__restrict__ acol, double *__restrict__ aneg,
+                               double *__restrict__ x0);
+__global__ void prep_dense_c128(int n, const perm_c128 *__restrict__ A, int64_t lda,
+                                double *__restrict__ acol, double *__restrict__ aneg,
+                                double *__restrict__ x0);
+
 // Sums `count` double-double partials (components interleaved: partial b of
 // component q is at p[b * comps + q]) in a fixed order with one block, and
 // writes scale * total (rounded to double) to out[q].

@@ -129,3 +129,24 @@ def test_sparse_argument_errors():
     assert f(2, cp.ctypes.data, ri.ctypes.data, v.ctypes.data, 3, FAKE, FAKE, big, None) == N.PERM_EINVAL
     assert f(2, cp.ctypes.data, ri.ctypes.data, v.ctypes.data, 2, None, FAKE, big, None) == N.PERM_EINVAL
     assert f(2, cp.ctypes.data, ri.ctypes.data, v.ctypes.data, 2, FAKE, None, 0, None) == N.PERM_EWORKSPACE
+
+
+def test_batched_plan_errors_and_workspace():
+    import ctypes
+    import numpy as np
+    lib = N.lib()
+    h = ctypes.c_void_p()
+    k = np.array([3, 33], np.int32)
+    off = np.array([0, 9], np.int64)
+    assert lib.perm_batched_plan_create(2, k.ctypes.data, off.ctypes.data, 1, ctypes.byref(h)) == N.PERM_EINVAL
+    k = np.array([3, 0], np.int32)
+    assert lib.perm_batched_plan_create(2, k.ctypes.data, off.ctypes.data, 1, ctypes.byref(h)) == N.PERM_EINVAL
+    assert lib.perm_batched_plan_create(0, k.ctypes.data, off.ctypes.data, 1, ctypes.byref(h)) == N.PERM_EINVAL
+    k = np.array([3, 24], np.int32)
+    assert lib.perm_batched_plan_create(2, k.ctypes.data, off.ctypes.data, 1, ctypes.byref(h)) == 0
+    nb = lib.perm_batched_workspace_bytes(h)
+    assert nb > 0
+    # too small a workspace, or a missing gradient buffer: refused before any GPU work
+    assert lib.perm_batched(h, FAKE, FAKE, FAKE, 1, FAKE, nb - 1, None) == N.PERM_EWORKSPACE
+    assert lib.perm_batched(h, FAKE, FAKE, None, 1, FAKE, nb, None) == N.PERM_EINVAL
+    lib.perm_plan_destroy(h)

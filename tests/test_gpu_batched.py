@@ -1,0 +1,133 @@
+"""Batched permanents + gradients (persistent launch, hipGraph) against the
+single-matrix paths and the oracle."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2502_16577_amd import api
+from paper_2502_16577_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def mixed_batch(ks, seed):
+    u = W.haar_unitary(64, seed)
+    rng = np.random.default_rng(seed + 1)
+    mats = []
+    for k in ks:
+        rows = rng.integers(0, 64, size=k)
+        cols = rng.integers(0, 64, size=k)
+        mats.append(np.ascontiguousarray(u[rows][:, cols]))
+    return mats
+
+
+def run(mats, want_grad=True, use_graph=True, autotune=False):
+    ks, offs, data = W.pack(mats)
+    plan = api.BatchedPlan(ks, offs, want_grad=want_grad)
+    d = torch.from_numpy(data).to(DEV)
+    if autotune:
+        plan.autotune(d)
+    out, grad = plan.run(d, use_graph=use_graph)
+    g = None
+    if grad is not None:
+        gh = grad.cpu().numpy()
+        g = [gh[o:o + k * k].reshape(k, k) for k, o in zip(ks, offs)]
+    return out.cpu().numpy(), g, plan, d
+
+
+KS = [1, 2, 3, 5, 7, 8, 9, 12, 13, 16, 17, 19, 20, 22, 24, 25, 27]
+
+
+def test_mixed_orders_vs_oracle(oracle):
+    mats = mixed_batch(KS, 31)
+    out, g, _, _ = run(mats)
+    for m, a in enumerate(mats):
+        want, r = oracle.ryser(a, with_abs=True)
+        assert abs(out[m] - want) <= 1e-10 * oracle.ryser(np.abs(a)), m
+        assert abs(out[m] - want) <= 1e-13 * r + 1e-300, (m, out[m], want, r)
+        k = a.shape[0]
+        if k <= 12:
+            gm = oracle.grad_minors(a)
+            for i in range(k):
+                for j in range(k):
+                    scale = oracle.perm(np.abs(np.delete(np.delete(a, i, 0), j, 1))) if k > 1 else 1.0
+                    assert abs(g[m][i, j] - gm[i, j]) <= 1e-10 * scale, (m, i, j)
+
+
+def test_matches_single_matrix_grad():
+    mats = mixed_batch([11, 14, 18, 21, 23], 41)
+    out, g, _, _ = run(mats)
+    for m, a in enumerate(mats):
+        p, gs = api.perm_grad(torch.from_numpy(a).to(DEV))
+        scale = np.max(np.abs(gs.cpu().numpy()))
+        assert abs(out[m] - p.item()) <= 1e-12 * max(abs(p.item()), 1e-300) + 1e-15 * scale
+        assert np.max(np.abs(g[m] - gs.cpu().numpy())) <= 1e-11 * scale
+
+
+def test_forward_only_plan_matches():
+    mats = mixed_batch([9, 15, 20], 51)
+    out_g, _, _, _ = run(mats, want_grad=True)
+    out_f, g, _, _ = run(mats, want_grad=False)
+    assert g is None
+    assert np.allclose(out_f, out_g, rtol=1e-12, atol=0)
+
+
+def test_graph_replays_match_eager():
+    mats = mixed_batch([8, 13, 17, 22, 24, 6], 61)
+    ks, offs, data = W.pack(mats)
+    plan = api.BatchedPlan(ks, offs, want_grad=True)
+    d = torch.from_numpy(data).to(DEV)
+    out_e, grad_e = plan.run(d, use_graph=False)
+    out_e, grad_e = out_e.clone(), grad_e.clone()
+    out, grad = plan.outputs(d)
+    for rep in range(3):
+        out.zero_()
+        grad.zero_()
+        plan.run(d, out=out, grad=grad, use_graph=True)
+        torch.cuda.synchronize()
+        junk = torch.randn(1 << 20, device=DEV).sum()  # eager work between replays
+        torch.cuda.synchronize()
+        assert torch.equal(out, out_e), rep
+        assert torch.equal(grad, grad_e), rep
+        del junk
+
+
+def test_autotune_keeps_results():
+    mats = mixed_batch([10, 16, 21, 23], 71)
+    out0, g0, _, _ = run(mats)
+    out1, g1, plan, _ = run(mats, autotune=True)
+    assert plan.info()["log2_chunk"] in (8, 10, 12)
+    for m in range(len(mats)):
+        assert abs(out1[m] - out0[m]) <= 1e-12 * abs(out0[m])
+        assert np.max(np.abs(g1[m] - g0[m])) <= 1e-11 * np.max(np.abs(g0[m]))
+
+
+def test_full_config_4096(oracle):
+    mats = W.batched_submatrices(4096, 8, 24)
+    out, g, plan, _ = run(mats)
+    rng = np.random.default_rng(5)
+    # permanents of a sample, against the oracle
+    for m in rng.choice(4096, size=12, replace=False):
+        a = mats[m]
+        if a.shape[0] > 20:
+            continue
+        want, r = oracle.ryser(a, with_abs=True)
+        assert abs(out[m] - want) <= 1e-10 * oracle.ryser(np.abs(a))
+        assert abs(out[m] - want) <= 1e-13 * r
+    # Laplace identity on every matrix: a_i . G_i = perm for each row
+    for m, a in enumerate(mats):
+        lhs = np.einsum("ij,ij->i", a, g[m])
+        scale = np.einsum("ij,ij->i", np.abs(a), np.abs(g[m])).max() + abs(out[m])
+        assert np.max(np.abs(lhs - out[m])) <= 1e-11 * scale, m
+    # sampled minors and finite differences
+    small = [m for m in range(4096) if mats[m].shape[0] <= 14]
+    for m in rng.choice(small, size=6, replace=False):
+        a = mats[m]
+        k = a.shape[0]
+        i, j = int(rng.integers(k)), int(rng.integers(k))
+        want = oracle.minor(a, i, j)
+        scale = oracle.perm(np.abs(np.delete(np.delete(a, i, 0), j, 1)))
+        assert abs(g[m][i, j] - want) <= 1e-10 * scale
+        fd = oracle.grad_fd(a, i, j)
+        assert abs(g[m][i, j] - fd) <= 1e-6 * max(abs(fd), 1e-300) or abs(g[m][i, j] - fd) <= 1e-10 * scale
