@@ -101,7 +101,8 @@ def bench_batched(reps: int = 5):
 
     # per-matrix perm_grad launches over the whole batch
     dm = [torch.from_numpy(a).to(dev) for a in mats]
-    wsg = torch.empty(api.workspace_bytes(6, 24), dtype=torch.uint8, device=dev)
+    wsg = torch.empty(max(api.workspace_bytes(6, n) for n in range(1, 25)), dtype=torch.uint8,
+                      device=dev)
     po = torch.empty((), dtype=torch.complex128, device=dev)
     go = torch.empty((24, 24), dtype=torch.complex128, device=dev)
     for a in dm[:64]:
@@ -116,7 +117,8 @@ def bench_batched(reps: int = 5):
     per_grad_ms = (time.perf_counter() - t0) * 1e3
 
     # plain forward solver: perm + every minor, one launch each (sampled per order)
-    wsp = torch.empty(api.workspace_bytes(2, 24), dtype=torch.uint8, device=dev)
+    wsp = torch.empty(max(api.workspace_bytes(2, n) for n in range(1, 25)), dtype=torch.uint8,
+                      device=dev)
     per_k = {}
     for k in sorted(set(int(x) for x in ks)):
         m = int(np.nonzero(ks == k)[0][0])
@@ -162,6 +164,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched perm+grad leg")
+    ap.add_argument("--only-batched", action="store_true",
+                    help="run only the batched perm+grad leg (prints its JSON object)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (3 times) and exit; "
                          "used to scale FETCH_SIZE / WRITE_SIZE counters to bytes")
@@ -176,6 +180,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read_per_launch": nbytes,
                           "copy_bytes_written_per_launch": nbytes, "launches": 3}))
+        return
+    if args.only_batched:
+        print(json.dumps(bench_batched()), flush=True)
         return
     if args.gpus != 1:
         print("bench.py: this build runs on exactly one GPU (no multi-GPU path); use --gpus 1",

@@ -1,0 +1,332 @@
+// One wave's share of the permanent-and-gradient sweep: 64 lanes, lane K =
+// 64 w + lane walks the Gray steps g in [K 2^c, (K+1) 2^c) of one matrix.
+// Shared by the single-matrix kernel (sweep_grad.hip) and the batched
+// persistent kernels (sweep_batched.hip).
+//
+// Gradient formula: with tau_j(g) = +1 if column j is in S_g or j = n-1, else
+// -1, and L_i(g) = prod_{k != i} x_k(g),
+//     dperm/da_ij = (-1)^(n-1) sum_g (-1)^g L_i(g) tau_j(g)
+// i.e. G = sum over subsets of the rank-1 updates V tau^T, V = (-1)^g L.
+//
+// The contraction is organised by the Gray code.  Split the local steps of
+// a lane into aligned windows of F = 2^f steps (f <= c - 1).  Inside a window
+// the bits of g from f upwards do not change, so tau_j is constant for every
+// column j >= f:
+//   * columns j >= f: the rank-1 updates of a window add up to W tau^T with
+//     W = sum of V over the window (one vector per lane); at the end of each
+//     window the 64 lanes' W are contracted with their tau as one FP64 MFMA
+//     product, G (n x n) += W (n x 64) T (64 x n), K running over the lanes.
+//   * columns j < f: tau_j depends only on the step (the same for every lane
+//     of the wave), so per step G[:, j] += tau_j U with U = sum over lanes of
+//     V; each lane sums 16 lanes' V from LDS and one MFMA per tile with the
+//     B operand tau_j repeated down K adds the four partial sums and forms the
+//     outer product with tau in one instruction.
+// MFMA operand layout (gfx950): A[i][k] at lane i + 16k, B[k][j] at lane
+// j + 16k, D[i][j] at lane j + 16 (i mod 4), register i / 4.
+// Accumulators fold into the item's double-double partial G in global memory
+// at the end of every window.
+#pragma once
+
+#include "sweep_common.h"
+
+namespace perm {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+template <bool CPLX>
+__device__ __forceinline__ void gmul(double &ar, double &ai, double br, double bi)
+{
+    if constexpr (CPLX) {
+        const double r = ar * br - ai * bi;
+        const double i = ar * bi + ai * br;
+        ar = r;
+        ai = i;
+    } else {
+        ar *= br;
+    }
+}
+
+__device__ __forceinline__ void wave_sync_lds()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int N, bool CPLX>
+struct GradItemShape {
+    static constexpr int MT = (N + 15) / 16;   // 16-row tiles of G
+    static constexpr int STRIDE = 16 * MT + 1;  // doubles per lane row in LDS
+    static constexpr int W = CPLX ? 2 : 1;      // components
+    static constexpr int LDS_DOUBLES = W * kWave * STRIDE;
+};
+
+// Inputs: staged acol / aneg ([j*N + i], W doubles per entry) and x0; the
+// wave index w; log2 chunk c >= 1; log2 re-seed interval r <= c - 1;
+// lanes_active (lanes with K >= lanes_active idle with x = 0).
+// Outputs: perm_out[0..1] (double-double re, im of the wave's share of
+// sum_g (-1)^g prod x), and, if want_grad, g_out[(i*N + j)*W + comp]
+// (double-double share of sum_g (-1)^g L_i tau_j, zeroed here).
+template <int N, bool CPLX>
+__device__ __forceinline__ void grad_item(const double *__restrict__ acol,
+                                          const double *__restrict__ aneg,
+                                          const double *__restrict__ x0, uint64_t w, int c, int r,
+                                          uint64_t lanes_active, dd *__restrict__ perm_out,
+                                          dd *__restrict__ g_out, bool want_grad,
+                                          double *__restrict__ lds)
+{
+    using S = GradItemShape<N, CPLX>;
+    constexpr int MT = S::MT;
+    constexpr int W = S::W;
+    constexpr int STRIDE = S::STRIDE;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t C = 1u << c;
+    const uint32_t rmask = (1u << r) - 1u;
+    const int f = c - 1 < 5 ? c - 1 : 5;  // window = 2^f steps
+    const uint32_t fmask = (1u << f) - 1u;
+    const uint64_t Kl = w * kWave + lane;
+    const double act = Kl < lanes_active ? 1.0 : 0.0;
+    const int jj = int(lane & 15u);      // B column / A row within a tile
+    const int kq = int(lane >> 4);       // K index within an MFMA (0..3)
+
+    double xr[N], xi[N];
+    double wr[N], wi[N];                 // window sums of V
+    v4d acc_lo[W][MT];                   // low columns (j < f), N-tile 0 only
+#pragma unroll
+    for (int q = 0; q < W; ++q)
+#pragma unroll
+        for (int a = 0; a < MT; ++a) acc_lo[q][a] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        wr[i] = 0.0;
+        wi[i] = 0.0;
+    }
+    if (want_grad)
+        for (int e = int(lane); e < W * N * N; e += kWave) g_out[e] = dd{0.0, 0.0};
+    double sr = 0.0, er = 0.0, si = 0.0, ei = 0.0;
+
+    auto reseed = [&](uint32_t l) {
+        const uint64_t g = (Kl << c) | l;
+        const uint64_t gray = g ^ (g >> 1);
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            xr[i] = act * x0[W * i];
+            xi[i] = CPLX ? act * x0[W * i + 1] : 0.0;
+        }
+        for (int j = 0; j < N - 1; ++j) {
+            const double fj = ((gray >> j) & 1u) ? act : 0.0;
+            const double *a = acol + W * j * N;
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                xr[i] = __builtin_fma(fj, a[W * i], xr[i]);
+                if (CPLX) xi[i] = __builtin_fma(fj, a[W * i + 1], xi[i]);
+            }
+        }
+    };
+    auto flip = [&](int j, bool add) {
+        const double *a = (add ? acol : aneg) + W * j * N;
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            xr[i] = __builtin_fma(act, a[W * i], xr[i]);
+            if (CPLX) xi[i] = __builtin_fma(act, a[W * i + 1], xi[i]);
+        }
+    };
+
+    // tau_j of the subset of lane `lk` at local step l (0 for padding columns).
+    auto tau = [&](uint64_t lk, uint32_t l, int j) -> double {
+        if (j >= N) return 0.0;
+        if (j == N - 1) return 1.0;
+        const uint64_t g = ((w * kWave + lk) << c) | l;
+        return (((g ^ (g >> 1)) >> j) & 1u) ? 1.0 : -1.0;
+    };
+
+    auto step = [&](uint32_t l) {
+        const double sg = (l & 1u) ? -1.0 : 1.0;  // (-1)^g = (-1)^l
+        // Leave-one-out products in four interleaved row blocks (four
+        // independent dependency chains): pass 1 forms prefix products inside
+        // each block and the block products P_b; then E_b = prod of the other
+        // blocks' P; pass 2 runs the suffix inside each block starting from
+        // sg * E_b, so L_i = prefix_i * sg * E_b * suffix_i.
+        constexpr int NB = N >= 8 ? 4 : 1;
+        constexpr int BS = (N + NB - 1) / NB;
+        double pr[N], pim[N];
+        double br[NB], bi[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            br[b] = 1.0;
+            bi[b] = 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t < BS; ++t)
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const int i = b * BS + t;
+                if (i < N) {
+                    pr[i] = br[b];
+                    pim[i] = bi[b];
+                    gmul<CPLX>(br[b], bi[b], xr[i], xi[i]);
+                }
+            }
+        double er_[NB], ei_[NB];  // E_b: product of the other blocks
+        {
+            double fr = 1.0, fi = 0.0;  // prefix over blocks
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                er_[b] = fr;
+                ei_[b] = fi;
+                gmul<CPLX>(fr, fi, br[b], bi[b]);
+            }
+            acc_add(sr, er, sg * fr);  // fr = the whole product
+            if (CPLX) acc_add(si, ei, sg * fi);
+            double gr = sg, gi = 0.0;  // suffix over blocks, with the sign
+#pragma unroll
+            for (int b = NB - 1; b >= 0; --b) {
+                gmul<CPLX>(er_[b], ei_[b], gr, gi);
+                gmul<CPLX>(gr, gi, br[b], bi[b]);
+            }
+        }
+        if (!want_grad) return;
+        double *vr = lds + lane * STRIDE;
+        double *vi = lds + (W - 1) * kWave * STRIDE + lane * STRIDE;
+#pragma unroll
+        for (int t = BS - 1; t >= 0; --t)
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const int i = b * BS + t;
+                if (i < N) {
+                    double lr = pr[i], li = pim[i];
+                    gmul<CPLX>(lr, li, er_[b], ei_[b]);
+                    wr[i] += lr;
+                    if (CPLX) wi[i] += li;
+                    if (f > 0) {
+                        vr[i] = lr;
+                        if (CPLX) vi[i] = li;
+                    }
+                    gmul<CPLX>(er_[b], ei_[b], xr[i], xi[i]);
+                }
+            }
+        if (f == 0) return;
+        wave_sync_lds();
+        // low columns j < f: lane sums 16 lanes' V (rows kq*16 .. +15) of
+        // matrix row i = 16a + jj; the MFMA adds the 4 partial sums and
+        // multiplies by tau_j(l) (the same for every lane).
+        const double bl = (jj < f) ? tau(0, l, jj) : 0.0;
+#pragma unroll
+        for (int a = 0; a < MT; ++a) {
+            const int i = 16 * a + jj;
+#pragma unroll
+            for (int q = 0; q < W; ++q) {
+                double s = 0.0;
+                if (i < N) {
+                    const double *col = lds + q * kWave * STRIDE + i + 16 * kq * STRIDE;
+                    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll
+                    for (int rr = 0; rr < 16; rr += 4) {
+                        s0 += col[rr * STRIDE];
+                        s1 += col[(rr + 1) * STRIDE];
+                        s2 += col[(rr + 2) * STRIDE];
+                        s3 += col[(rr + 3) * STRIDE];
+                    }
+                    s = (s0 + s1) + (s2 + s3);
+                }
+                acc_lo[q][a] = __builtin_amdgcn_mfma_f64_16x16x4f64(s, bl, acc_lo[q][a], 0, 0, 0);
+            }
+        }
+        wave_sync_lds();
+    };
+
+    // End of a window: contract the lanes' window sums with their tau for
+    // the columns j >= f, then fold everything into the double-double G.
+    auto close_window = [&](uint32_t l0) {
+        v4d acc_hi[W][MT][MT];  // the window's contraction
+#pragma unroll
+        for (int q = 0; q < W; ++q)
+#pragma unroll
+            for (int a = 0; a < MT; ++a)
+#pragma unroll
+                for (int b = 0; b < MT; ++b) acc_hi[q][a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+        double *vr = lds + lane * STRIDE;
+        double *vi = lds + (W - 1) * kWave * STRIDE + lane * STRIDE;
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            vr[i] = wr[i];
+            if (CPLX) vi[i] = wi[i];
+            wr[i] = 0.0;
+            wi[i] = 0.0;
+        }
+        wave_sync_lds();
+#pragma unroll 2
+        for (int q4 = 0; q4 < 16; ++q4) {
+            const uint64_t lk = uint64_t(4 * q4 + kq);  // lane (subset) of this K row
+            double bop[MT];
+#pragma unroll
+            for (int b = 0; b < MT; ++b) {
+                const int j = 16 * b + jj;
+                bop[b] = (j >= f) ? tau(lk, l0, j) * (lk < lanes_active ? 1.0 : 0.0) : 0.0;
+            }
+#pragma unroll
+            for (int a = 0; a < MT; ++a) {
+                const int i = 16 * a + jj;
+#pragma unroll
+                for (int q = 0; q < W; ++q) {
+                    const double av = (i < N) ? lds[q * kWave * STRIDE + lk * STRIDE + i] : 0.0;
+#pragma unroll
+                    for (int b = 0; b < MT; ++b)
+                        acc_hi[q][a][b] =
+                            __builtin_amdgcn_mfma_f64_16x16x4f64(av, bop[b], acc_hi[q][a][b], 0, 0, 0);
+                }
+            }
+        }
+        wave_sync_lds();
+        // fold into the item's partial G
+#pragma unroll
+        for (int q = 0; q < W; ++q)
+#pragma unroll
+            for (int a = 0; a < MT; ++a)
+#pragma unroll
+                for (int b = 0; b < MT; ++b) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int i = 16 * a + kq + 4 * e;
+                        const int j = 16 * b + jj;
+                        double v = acc_hi[q][a][b][e];
+                        if (b == 0) v += acc_lo[q][a][e];
+                        if (i < N && j < N) {
+                            dd *p = g_out + (i * N + j) * W + q;
+                            const dd o = *p;
+                            double s, t;
+                            two_sum(o.hi, v, s, t);
+                            *p = dd{s, o.lo + t};
+                        }
+                    }
+                    if (b == 0) acc_lo[q][a] = v4d{0.0, 0.0, 0.0, 0.0};
+                }
+    };
+
+    for (uint32_t l = 0; l < C; l += 2) {
+        if ((l & rmask) == 0) {
+            reseed(l);
+        } else {
+            const int j = __builtin_ctz(l);
+            flip(j, (((l ^ (l >> 1)) >> j) & 1u) != 0u);
+        }
+        step(l);
+        if (want_grad && f == 0) close_window(l);
+        if (c == 1) {
+            reseed(l + 1);  // the column-0 sign depends on the lane when c == 1
+        } else {
+            const uint32_t l1 = l + 1;
+            flip(0, ((l1 ^ (l1 >> 1)) & 1u) != 0u);
+        }
+        step(l + 1);
+        if (want_grad && ((l + 2) & fmask) == 0) close_window((l + 1) & ~fmask);
+    }
+    const dd pr = wave_reduce_dd(dd{sr, er});
+    const dd pi = wave_reduce_dd(dd{si, ei});
+    if (lane == 0) {
+        perm_out[0] = pr;
+        perm_out[1] = pi;
+    }
+}
+
+}  // namespace perm

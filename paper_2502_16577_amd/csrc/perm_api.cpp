@@ -91,9 +91,8 @@ GradWs grad_ws_layout(int n, int components, int64_t waves)
     L.perm_partials = off;
     off += align256(size_t(std::max<int64_t>(waves, 1)) * 2 * sizeof(dd));
     L.grad_partials = off;
-    const size_t tiles = size_t((n + 15) / 16) * size_t((n + 15) / 16);
-    off += align256(size_t(std::max<int64_t>(waves, 1)) * size_t(components) * tiles * 4 * kWave *
-                    sizeof(dd));
+    off += align256(size_t(std::max<int64_t>(waves, 1)) * size_t(components) * size_t(n) *
+                    size_t(n) * sizeof(dd));
     L.total = off;
     return L;
 }
@@ -185,17 +184,16 @@ size_t perm_workspace_bytes(int kind, int n, int64_t m)
     (void)m;
     if (!valid_n(n)) return 0;
     switch (kind) {
-    case PERM_KIND_DENSE_F64: {
-        const SweepPlan p = plan_sweep(n, 0);
-        return dense_ws_layout(n, 1, p.blocks).total;
-    }
+    case PERM_KIND_DENSE_F64:
     case PERM_KIND_DENSE_C128: {
+        const int comps = kind == PERM_KIND_DENSE_C128 ? 2 : 1;
+        if (n <= kSmallN) return grad_ws_layout(n, comps, plan_grad(n).waves).total;
         const SweepPlan p = plan_sweep(n, 0);
-        return dense_ws_layout(n, 2, p.blocks).total;
+        return dense_ws_layout(n, comps, p.blocks).total;
     }
     case PERM_KIND_SPARSE_F64: {
-        const SweepPlan p = plan_sweep(n, 0);
-        return dense_ws_layout(n, 1, p.blocks).total + align256(size_t(n) * n * sizeof(double));
+        return perm_workspace_bytes(PERM_KIND_DENSE_F64, n, 0) +
+               align256(size_t(n) * n * sizeof(double));
     }
     case PERM_KIND_GRAD_F64:
     case PERM_KIND_GRAD_C128: {
@@ -245,8 +243,7 @@ int perm_sparse_f64(int n, const int32_t *col_ptr, const int32_t *row_idx, const
     if (n == 0) return launch_dense_f64(0, nullptr, 0, out, base, st);
     // Stage the matrix row-major behind the dense workspace; the sweep then
     // updates x with whole columns held in scalar registers (zeros included).
-    const SweepPlan p = plan_sweep(n, 0);
-    const size_t off = dense_ws_layout(n, 1, p.blocks).total;
+    const size_t off = perm_workspace_bytes(PERM_KIND_DENSE_F64, n, 0);
     std::vector<double> dense(size_t(n) * n, 0.0);
     for (int j = 0; j < n; ++j)
         for (int32_t q = col_ptr[j]; q < col_ptr[j + 1]; ++q) dense[size_t(row_idx[q]) * n + j] = vals[q];

@@ -17,6 +17,7 @@ constexpr int kBlock = 256;          // threads per block: 4 waves of 64
 constexpr int kWave = 64;
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kMaxPrimes = 5;        // binary path: at most 5 primes of 61 bits
+constexpr int kSmallN = 12;          // n <= 12: forward sweeps run on the one-wave gradient kernel
 
 // Gray-walk decomposition of the 2^(n-1) steps of one matrix:
 //   lanes * 2^log2_chunk == 2^(n-1), every lane walks one contiguous chunk,
@@ -89,14 +90,14 @@ struct BinaryWs {
 
 BinaryWs binary_ws_layout(int n, int64_t blocks);
 
-// Gradient sweep: one wave per block, `waves` waves, lanes = 64 * waves.
-constexpr int kGradSerialMaxN = 10;  // n <= 10: one lane, direct formula
+// Gradient sweep (and the forward sweep of small n): one wave per block.
 constexpr int kGradMaxN = 32;        // MFMA tiles of G up to 2 x 2
 
 struct GradPlan {
     int n = 0;
-    int log2_chunk = 0;
-    int log2_reseed = 0;
+    int log2_chunk = 0;       // c >= 1 (n >= 2)
+    int log2_reseed = 0;      // r <= c - 1
+    int64_t lanes_active = 0; // 2^(n-1-c); lanes beyond it idle (small n)
     int64_t waves = 0;
 };
 
@@ -105,7 +106,7 @@ GradPlan plan_grad(int n);
 struct GradWs {
     size_t acol = 0, aneg = 0, x0 = 0;  // as DenseWs
     size_t perm_partials = 0;           // waves * 2 dd
-    size_t grad_partials = 0;           // waves * components * tiles * 4 * 64 dd
+    size_t grad_partials = 0;           // waves * components * n * n dd
     size_t total = 0;
 };
 
@@ -122,6 +123,9 @@ int launch_dense_c128(int n, const perm_c128 *A, int64_t lda, perm_c128 *out, ch
 // Permanent and dperm/dA (row-major n x n, interleaved if complex).
 int launch_grad(int n, bool cplx, const void *A, int64_t lda, void *out_perm, void *out_grad,
                 char *ws, hipStream_t stream);
+// The same sweep without the gradient (used for the forward path of n <= 12).
+int launch_grad_or_small(int n, bool cplx, const void *A, int64_t lda, void *out_perm,
+                         void *out_grad, bool want_grad, char *ws, hipStream_t stream);
 // Residues R_k = sum_g (-1)^g prod_i y_i(g) mod p_k (k < nprimes) into residues_dev.
 int launch_binary_residues(int n, const double *dense01, int nprimes, uint64_t *residues_dev,
                            char *ws, hipStream_t stream);

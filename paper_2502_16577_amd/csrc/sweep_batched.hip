@@ -10,27 +10,14 @@
 // segmented finalize sums the items of every matrix in a fixed order, so the
 // result does not depend on which wave ran which item.
 //
-// Per item the arithmetic is the one of sweep_grad.hip: x in VGPRs, the
-// flipped column read with scalar loads, an exact re-seed of x every 2^r
-// steps, leave-one-out products into LDS, and the rank-1 updates of the 64
-// subsets of one step contracted with v_mfma_f64_16x16x4f64.  Because the
-// lane index enters the Gray code from bit c upwards, the only flip whose sign
-// depends on the lane is the one at l = 2^(c-1); r <= c - 1 makes that step a
-// re-seed, so every incremental flip is wave-uniform.
+// Per item the arithmetic is grad_item (grad_item.h), the same as for a
+// single matrix: x in VGPRs, the flipped column read with scalar loads, an
+// exact re-seed of x every 2^r steps, leave-one-out products, and the
+// gradient contraction organised by Gray-code windows with FP64 MFMA.
 #include "batched_internal.h"
-#include "sweep_common.h"
+#include "grad_item.h"
 
 namespace perm {
-
-typedef double v4d __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ void cmulb(double &ar, double &ai, double br, double bi)
-{
-    const double r = ar * br - ai * bi;
-    const double i = ar * bi + ai * br;
-    ar = r;
-    ai = i;
-}
 
 // Stages every matrix: acol[2(j k + i) + {re,im}], aneg = -acol, x0[2 i + {re,im}]
 // at stage + mats[m].stage (doubles).  One block per matrix.
@@ -68,205 +55,34 @@ __global__ void batched_reset(uint32_t *counters, int n)
     if (int(threadIdx.x) < n) counters[threadIdx.x] = 0u;
 }
 
-constexpr int kBatchFoldPairs = 16;
-
 template <int K>
 __device__ __forceinline__ void batched_item(const BatchMatDev &M, int w,
                                              const double *__restrict__ stage,
                                              dd *__restrict__ perm_out, dd *__restrict__ g_out,
                                              bool want_grad, double *__restrict__ lds)
 {
-    constexpr int MT = (K + 15) / 16;
-    constexpr int STRIDE = 16 * MT + 1;
-    const uint32_t lane = threadIdx.x & 63u;
     const double *acol = stage + M.stage;
-    const double *aneg = acol + 2 * K * K;
-    const double *x0 = aneg + 2 * K * K;
-    const int c = M.c;
-    const uint32_t C = 1u << c;
-    const uint32_t rmask = (1u << M.r) - 1u;
-    const uint64_t lanes_active = (uint64_t(1) << (K - 1)) >> c;
-    const uint64_t Kl = uint64_t(w) * kWave + lane;
-    const double act = Kl < lanes_active ? 1.0 : 0.0;
-    const int jcol0 = int(lane & 15u);
-
-    if (K == 1) {  // one subset: perm = a, G = [1]
-        if (lane == 0) {
-            perm_out[0] = dd{0.5 * acol[0], 0.0};  // finalize multiplies by 2
+    if constexpr (K == 1) {  // one subset: perm = a, G = [1]
+        if ((threadIdx.x & 63u) == 0) {
+            perm_out[0] = dd{0.5 * acol[0], 0.0};  // the finalize multiplies by 2
             perm_out[1] = dd{0.5 * acol[1], 0.0};
             if (want_grad) {
                 g_out[0] = dd{1.0, 0.0};
                 g_out[1] = dd{0.0, 0.0};
             }
         }
-        return;
-    }
-
-    double xr[K], xi[K];
-    v4d accm[2][MT][MT];
-#pragma unroll
-    for (int q = 0; q < 2; ++q)
-#pragma unroll
-        for (int a = 0; a < MT; ++a)
-#pragma unroll
-            for (int b = 0; b < MT; ++b) accm[q][a][b] = v4d{0.0, 0.0, 0.0, 0.0};
-    if (want_grad)
-        for (int e = int(lane); e < 2 * K * K; e += kWave) g_out[e] = dd{0.0, 0.0};
-    double sr = 0.0, er = 0.0, si = 0.0, ei = 0.0;
-
-    auto reseed = [&](uint32_t l) {
-        const uint64_t g = (Kl << c) | l;
-        const uint64_t gray = g ^ (g >> 1);
-#pragma unroll
-        for (int i = 0; i < K; ++i) {
-            xr[i] = act * x0[2 * i];
-            xi[i] = act * x0[2 * i + 1];
-        }
-        for (int j = 0; j < K - 1; ++j) {
-            const double f = ((gray >> j) & 1u) ? act : 0.0;
-            const double *a = acol + 2 * j * K;
-#pragma unroll
-            for (int i = 0; i < K; ++i) {
-                xr[i] = __builtin_fma(f, a[2 * i], xr[i]);
-                xi[i] = __builtin_fma(f, a[2 * i + 1], xi[i]);
-            }
-        }
-    };
-    auto flip = [&](int j, bool add) {
-        const double *a = (add ? acol : aneg) + 2 * j * K;
-#pragma unroll
-        for (int i = 0; i < K; ++i) {
-            xr[i] = __builtin_fma(act, a[2 * i], xr[i]);
-            xi[i] = __builtin_fma(act, a[2 * i + 1], xi[i]);
-        }
-    };
-    auto step = [&](uint32_t l) {
-        const bool neg = l & 1u;
-        double *vr = lds + lane * STRIDE;
-        double *vi = lds + kWave * STRIDE + lane * STRIDE;
-        double pr = 1.0, pi = 0.0;
-        if (want_grad) {
-#pragma unroll
-            for (int i = 0; i < K; ++i) {
-                vr[i] = pr;
-                vi[i] = pi;
-                cmulb(pr, pi, xr[i], xi[i]);
-            }
-        } else {
-            double r0 = xr[0], i0 = xi[0], r1 = 1.0, i1 = 0.0;
-#pragma unroll
-            for (int i = 1; i < K; i += 2) {
-                cmulb(r1, i1, xr[i], xi[i]);
-                if (i + 1 < K) cmulb(r0, i0, xr[i + 1], xi[i + 1]);
-            }
-            cmulb(r0, i0, r1, i1);
-            pr = r0;
-            pi = i0;
-        }
-        acc_add(sr, er, neg ? -pr : pr);
-        acc_add(si, ei, neg ? -pi : pi);
-        if (!want_grad) return;
-        double sufr = 1.0, sufi = 0.0;
-#pragma unroll
-        for (int i = K - 1; i >= 0; --i) {
-            double lr = vr[i], li = vi[i];
-            cmulb(lr, li, sufr, sufi);
-            vr[i] = lr;
-            vi[i] = li;
-            cmulb(sufr, sufi, xr[i], xi[i]);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const double sg = neg ? -1.0 : 1.0;
-#pragma unroll 2
-        for (int q = 0; q < 16; ++q) {
-            const uint32_t kl = uint32_t(4 * q) + (lane >> 4);
-            const uint64_t Kq = uint64_t(w) * kWave + kl;
-            const uint64_t g = (Kq << c) | l;
-            const uint64_t gray = g ^ (g >> 1);
-            const double sq = Kq < lanes_active ? sg : 0.0;
-            double bop[MT];
-#pragma unroll
-            for (int b = 0; b < MT; ++b) {
-                const int j = 16 * b + jcol0;
-                double t = ((gray >> j) & 1u) ? sq : -sq;
-                if (j == K - 1) t = sq;
-                if (j >= K) t = 0.0;
-                bop[b] = t;
-            }
-#pragma unroll
-            for (int a = 0; a < MT; ++a) {
-                const int i = 16 * a + jcol0;
-                const double are = (i < K) ? lds[kl * STRIDE + i] : 0.0;
-                const double aim = (i < K) ? lds[kWave * STRIDE + kl * STRIDE + i] : 0.0;
-#pragma unroll
-                for (int b = 0; b < MT; ++b) {
-                    accm[0][a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(are, bop[b], accm[0][a][b], 0, 0, 0);
-                    accm[1][a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(aim, bop[b], accm[1][a][b], 0, 0, 0);
-                }
-            }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    };
-    auto fold = [&]() {
-#pragma unroll
-        for (int q = 0; q < 2; ++q)
-#pragma unroll
-            for (int a = 0; a < MT; ++a)
-#pragma unroll
-                for (int b = 0; b < MT; ++b) {
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const int i = 16 * a + int(lane >> 4) + 4 * e;
-                        const int j = 16 * b + jcol0;
-                        if (i < K && j < K) {
-                            dd *p = g_out + (i * K + j) * 2 + q;
-                            const dd v = *p;
-                            double s, t;
-                            two_sum(v.hi, accm[q][a][b][e], s, t);
-                            *p = dd{s, v.lo + t};
-                        }
-                    }
-                    accm[q][a][b] = v4d{0.0, 0.0, 0.0, 0.0};
-                }
-    };
-
-    uint32_t pairs = 0;
-    for (uint32_t l = 0; l < C; l += 2) {
-        if ((l & rmask) == 0) {
-            reseed(l);
-        } else {
-            const int j = __builtin_ctz(l);
-            flip(j, (((l ^ (l >> 1)) >> j) & 1u) != 0u);
-        }
-        step(l);
-        if (c == 1) {
-            reseed(l + 1);  // the column-0 sign depends on the lane when c == 1
-        } else {
-            const uint32_t l1 = l + 1;
-            flip(0, ((l1 ^ (l1 >> 1)) & 1u) != 0u);
-        }
-        step(l + 1);
-        if (want_grad && ++pairs == kBatchFoldPairs) {
-            fold();
-            pairs = 0;
-        }
-    }
-    if (want_grad) fold();
-    const dd pr = wave_reduce_dd(dd{sr, er});
-    const dd pim = wave_reduce_dd(dd{si, ei});
-    if (lane == 0) {
-        perm_out[0] = pr;
-        perm_out[1] = pim;
+    } else {
+        const double *aneg = acol + 2 * K * K;
+        const double *x0 = aneg + 2 * K * K;
+        const uint64_t lanes_active = (uint64_t(1) << (K - 1)) >> M.c;
+        grad_item<K, true>(acol, aneg, x0, uint64_t(w), M.c, M.r, lanes_active, perm_out, g_out,
+                           want_grad, lds);
     }
 }
 
 template <int K0, int K1>
 struct BatchDispatch {
-    __device__ static void run(int k, const BatchMatDev &M, int w, const double *stage, dd *pp,
+    __device__ __forceinline__ static void run(int k, const BatchMatDev &M, int w, const double *stage, dd *pp,
                                dd *gp, bool want_grad, double *lds)
     {
         if (k == K0) batched_item<K0>(M, w, stage, pp, gp, want_grad, lds);
@@ -281,8 +97,7 @@ __global__ __launch_bounds__(kWave) void batched_persistent(
     uint32_t *__restrict__ counter, const double *__restrict__ stage,
     dd *__restrict__ perm_parts, dd *__restrict__ g_parts, int want_grad)
 {
-    constexpr int MT = (K1 + 15) / 16;
-    __shared__ double lds[2 * kWave * (16 * MT + 1)];
+    __shared__ double lds[GradItemShape<K1, true>::LDS_DOUBLES];
     for (;;) {
         uint32_t it = 0;
         if (threadIdx.x == 0) it = atomicAdd(counter, 1u);

@@ -36,49 +36,12 @@ __global__ __launch_bounds__(kBlock) void prep_dense_c128(int n, const perm_c128
     }
 }
 
-constexpr int kSerialSmallNc = 12;
-
 __device__ __forceinline__ void cmul(double &ar, double &ai, double br, double bi)
 {
     const double r = ar * br - ai * bi;
     const double i = ar * bi + ai * br;
     ar = r;
     ai = i;
-}
-
-__global__ void serial_dense_c128(int n, const double *__restrict__ acol,
-                                  const double *__restrict__ aneg,
-                                  const double *__restrict__ x0, dd *__restrict__ partials)
-{
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    double xr[kSerialSmallNc], xi[kSerialSmallNc];
-    for (int i = 0; i < n; ++i) {
-        xr[i] = x0[2 * i];
-        xi[i] = x0[2 * i + 1];
-    }
-    double sr = 0.0, er = 0.0, si = 0.0, ei = 0.0;
-    double pr = 1.0, pi = 0.0;
-    for (int i = 0; i < n; ++i) cmul(pr, pi, xr[i], xi[i]);
-    acc_add(sr, er, pr);
-    acc_add(si, ei, pi);
-    const uint32_t steps = 1u << (n - 1);
-    for (uint32_t g = 1; g < steps; ++g) {
-        const int j = __builtin_ctz(g);
-        const bool add = ((g ^ (g >> 1)) >> j) & 1u;
-        const double *a = (add ? acol : aneg) + 2 * j * n;
-        pr = 1.0;
-        pi = 0.0;
-        for (int i = 0; i < n; ++i) {
-            xr[i] += a[2 * i];
-            xi[i] += a[2 * i + 1];
-            cmul(pr, pi, xr[i], xi[i]);
-        }
-        const bool odd = g & 1u;
-        acc_add(sr, er, odd ? -pr : pr);
-        acc_add(si, ei, odd ? -pi : pi);
-    }
-    partials[0] = dd{sr, er};
-    partials[1] = dd{si, ei};
 }
 
 template <int N>
@@ -225,17 +188,15 @@ int launch_dense_c128(int n, const perm_c128 *A, int64_t lda, perm_c128 *out, ch
     double *aneg = reinterpret_cast<double *>(ws + L.aneg);
     double *x0 = reinterpret_cast<double *>(ws + L.x0);
     dd *partials = reinterpret_cast<dd *>(ws + L.partials);
+    if (n <= kSmallN)  // one or a few waves: the gradient sweep's kernel without the gradient
+        return launch_grad_or_small(n, true, A, lda, out, nullptr, false, ws, stream);
     hipLaunchKernelGGL(prep_dense_c128, dim3(1), dim3(kBlock), 0, stream, n, A, lda, acol, aneg,
                        x0);
-    int64_t nparts = 1;
-    if (n <= kSerialSmallNc) {
-        hipLaunchKernelGGL(serial_dense_c128, dim3(1), dim3(64), 0, stream, n, acol, aneg, x0,
-                           partials);
-    } else {
+    const int64_t nparts = p.blocks;
+    {
         CSweepLauncher f = DenseC128Table::get(n);
         if (!f) return PERM_EUNSUPPORTED;
         f(p, acol, aneg, x0, partials, stream);
-        nparts = p.blocks;
     }
     const double scale = (n & 1) ? 2.0 : -2.0;
     hipLaunchKernelGGL(finalize_partials, dim3(1), dim3(kBlock), 0, stream, partials, nparts, 2,

@@ -37,35 +37,6 @@ __global__ __launch_bounds__(kBlock) void prep_dense_f64(int n, const double *__
     }
 }
 
-// n <= kSerialSmallN: one lane runs Algorithm 1 directly (at most 2^11 steps).
-constexpr int kSerialSmallN = 12;
-
-__global__ void serial_dense_f64(int n, const double *__restrict__ acol,
-                                 const double *__restrict__ aneg,
-                                 const double *__restrict__ x0, dd *__restrict__ partials)
-{
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    double x[kSerialSmallN];
-    for (int i = 0; i < n; ++i) x[i] = x0[i];
-    double s = 0.0, e = 0.0;
-    double p = 1.0;
-    for (int i = 0; i < n; ++i) p *= x[i];
-    acc_add(s, e, p);
-    const uint32_t steps = 1u << (n - 1);
-    for (uint32_t g = 1; g < steps; ++g) {
-        const int j = __builtin_ctz(g);
-        const bool add = ((g ^ (g >> 1)) >> j) & 1u;
-        const double *a = (add ? acol : aneg) + j * n;
-        p = 1.0;
-        for (int i = 0; i < n; ++i) {
-            x[i] += a[i];
-            p *= x[i];
-        }
-        acc_add(s, e, (g & 1u) ? -p : p);
-    }
-    partials[0] = dd{s, e};
-}
-
 template <int N>
 __device__ __forceinline__ double product4(const double (&x)[N])
 {
@@ -191,16 +162,14 @@ int launch_dense_f64(int n, const double *A, int64_t lda, double *out, char *ws,
     double *aneg = reinterpret_cast<double *>(ws + L.aneg);
     double *x0 = reinterpret_cast<double *>(ws + L.x0);
     dd *partials = reinterpret_cast<dd *>(ws + L.partials);
+    if (n <= kSmallN)  // one or a few waves: the gradient sweep's kernel without the gradient
+        return launch_grad_or_small(n, false, A, lda, out, nullptr, false, ws, stream);
     hipLaunchKernelGGL(prep_dense_f64, dim3(1), dim3(kBlock), 0, stream, n, A, lda, acol, aneg, x0);
-    int64_t nparts = 1;
-    if (n <= kSerialSmallN) {
-        hipLaunchKernelGGL(serial_dense_f64, dim3(1), dim3(64), 0, stream, n, acol, aneg, x0,
-                           partials);
-    } else {
+    const int64_t nparts = p.blocks;
+    {
         SweepLauncher f = DenseF64Table::get(n);
         if (!f) return PERM_EUNSUPPORTED;
         f(p, acol, aneg, x0, partials, stream);
-        nparts = p.blocks;
     }
     const double scale = (n & 1) ? 2.0 : -2.0;  // 2 (-1)^(n-1)
     hipLaunchKernelGGL(finalize_partials, dim3(1), dim3(kBlock), 0, stream, partials, nparts, 1,
