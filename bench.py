@@ -157,6 +157,50 @@ def bench_batched(reps: int = 5):
     }
 
 
+# Best published GPU kernel (x_reg-A_shr-rebuild with CEG, Quadro GV100) of
+# Table 4 and the precision study of Table 3 (GV100), in seconds / relative error.
+PAPER_TABLE4_GV100_S = {30: 0.83, 32: 0.93, 35: 1.20, 40: 14.17, 45: 528.98, 48: 4326.23}
+PAPER_TABLE4_CPU44_S = {30: 0.65, 32: 2.74, 35: 23.15, 40: 835.50, 45: 30323.30, 48: 256779.81}
+PAPER_TABLE3_GV100 = {35: {"DD": 1.40e-9, "Kahan": 8.78e-12, "DD_s": 1.31, "Kahan_s": 1.34},
+                      40: {"DD": 2.69e-7, "Kahan": 6.63e-11, "DD_s": 14.25, "Kahan_s": 14.78},
+                      45: {"DD": 1.49e-4, "Kahan": 2.34e-10, "DD_s": 496.34, "Kahan_s": 526.46}}
+
+
+def paper_tables(sizes):
+    """Table 4 shapes (dense U[0,1), one matrix per n) and Table 3 shapes (all
+    entries 0.91, perm = n! 0.91^n) on this GPU; one JSON line per row."""
+    import math
+    import numpy as np
+    import torch
+    from paper_2502_16577_amd import api, workloads
+
+    dev = torch.device("cuda:0")
+    for n in sizes:
+        a = workloads.uniform(n, 1000 + n)
+        A = torch.from_numpy(a).to(dev)
+        api.perm_dense_f64(A)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        v = api.perm_dense_f64(A).item()
+        dt = time.perf_counter() - t0
+        print(json.dumps({"table": 4, "n": n, "workload": f"dense {n}x{n} U[0,1) seed {1000 + n}",
+                          "seconds": dt, "subset_steps_per_s": 2 ** (n - 1) / dt, "perm": v,
+                          "paper_gv100_s": PAPER_TABLE4_GV100_S.get(n),
+                          "paper_cpu44_s": PAPER_TABLE4_CPU44_S.get(n)}), flush=True)
+        J = torch.full((n, n), 0.91, dtype=torch.float64, device=dev)
+        exact = math.factorial(n) * 0.91 ** n
+        for name, acc in (("twosum", api.ACC_TWOSUM), ("kahan", api.ACC_KAHAN),
+                          ("plain", api.ACC_PLAIN)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            v = api.perm_dense_f64_ex(J, accumulation=acc).item()
+            dt = time.perf_counter() - t0
+            print(json.dumps({"table": 3, "n": n, "accumulation": name,
+                              "workload": f"all entries 0.91, {n}x{n}",
+                              "rel_error": abs(v - exact) / exact, "seconds": dt,
+                              "paper_gv100": PAPER_TABLE3_GV100.get(n)}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -164,6 +208,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched perm+grad leg")
+    ap.add_argument("--paper-tables", type=str, default="",
+                    help="comma-separated n: time the paper's Table 4 / Table 3 shapes and exit")
     ap.add_argument("--only-batched", action="store_true",
                     help="run only the batched perm+grad leg (prints its JSON object)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -180,6 +226,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read_per_launch": nbytes,
                           "copy_bytes_written_per_launch": nbytes, "launches": 3}))
+        return
+    if args.paper_tables:
+        paper_tables([int(x) for x in args.paper_tables.split(",")])
         return
     if args.only_batched:
         print(json.dumps(bench_batched()), flush=True)

@@ -90,6 +90,26 @@ size_t perm_workspace_bytes(int kind, int n, int64_t m);
 int perm_dense_f64(int n, const double *A, int64_t lda, double *out,
                    void *ws, size_t ws_bytes, void *stream);
 
+/* Options of perm_dense_f64_ex (zero-initialise for the defaults). */
+/* Lane accumulation modes (Section 5, Table 3); block and grid partials are
+ * always combined in double-double (the paper's "quad" outer sum). */
+#define PERM_ACC_TWOSUM 0  /* two-sum: the lane partial is a double-double ("DQ"); the default */
+#define PERM_ACC_PLAIN  1  /* plain double lane partial ("DD") */
+#define PERM_ACC_KAHAN  2  /* Kahan-compensated lane partial ("Kahan") */
+
+typedef struct {
+    int accumulation;              /* PERM_ACC_TWOSUM, PERM_ACC_PLAIN or PERM_ACC_KAHAN */
+    int log2_reseed;               /* exact re-seed of x every 2^r steps; 0 = default (2^9),
+                                      values above the lane's chunk mean once per chunk */
+    int64_t max_steps_per_launch;  /* 0 = default (2^40): longer sweeps are split into
+                                      several launches over consecutive lane ranges */
+} perm_options;
+
+/* perm_dense_f64 with options (opt may be NULL).  PERM_EINVAL for an unknown
+ * accumulation mode or negative fields. */
+int perm_dense_f64_ex(int n, const double *A, int64_t lda, const perm_options *opt,
+                      double *out, void *ws, size_t ws_bytes, void *stream);
+
 /*
  * Permanent of a dense complex n x n matrix: the same sweep with complex x
  * and complex products (Section 1 lists complex matrices among the supported
@@ -207,6 +227,44 @@ int perm_batched_autotune(perm_plan *plan, const perm_c128 *data, perm_c128 *out
 /* Plan introspection: number of work items, chosen log2 steps per lane, grid. */
 int perm_batched_plan_info(const perm_plan *plan, int64_t *n_items, int *log2_chunk,
                            int64_t *grid_small);
+
+/* out = sum_m weights[m] * perms[m] over count >= 1 device values, in
+ * double-double and a fixed order (used to combine the leaves of a
+ * decomposition).  Asynchronous on `stream`. */
+int perm_weighted_sum(int count, const double *weights, const perm_c128 *perms, perm_c128 *out,
+                      void *stream);
+
+/*
+ * Sparse preprocessing of Section 4 (host only, no GPU work).
+ *   PERM_DECOMP_DM  fine-grain Dulmage-Mendelsohn pruning (Section 4.1):
+ *                   find a perfect matching, orient matching edges row ->
+ *                   column and the others column -> row, and delete every
+ *                   nonzero whose row and column lie in different strongly
+ *                   connected components (it lies on no perfect matching);
+ *                   no perfect matching means perm = 0 (no leaves).
+ *   PERM_DECOMP_FM  Algorithm 4 (DecompRyser): while a row or column has at
+ *                   most 4 nonzeros, remove it by the Forbert-Marx expansion
+ *                   (Eq. (expand)): 1 nonzero -> alpha * perm(minor), 2 -> the
+ *                   merged (n-1) x (n-1) matrix, 3 or 4 -> two matrices
+ *                   (at most 2^16 such two-way splits per call; after that
+ *                   the remaining matrices are leaves).
+ * The result is a list of leaves (k_m, weight_m, k_m x k_m row-major matrix)
+ * with perm(A) = sum_m weight_m perm(leaf_m); a leaf of order 0 is stored as
+ * the 1 x 1 matrix [1].  min_leaf stops decomposing matrices of that order or
+ * less.  PERM_ERANGE if more than 2^22 leaves would be produced.
+ */
+#define PERM_DECOMP_DM 1
+#define PERM_DECOMP_FM 2
+
+typedef struct perm_decomp perm_decomp;
+
+int perm_decompose(int n, const int32_t *col_ptr, const int32_t *row_idx, const double *vals,
+                   int32_t nnz, int flags, int min_leaf, perm_decomp **out);
+int perm_decomp_info(const perm_decomp *d, int *count, int *max_order, int64_t *total_elements,
+                     int64_t *removed_nonzeros);
+/* Leaf idx: order, weight and (if data is non-NULL) its k*k entries. */
+int perm_decomp_leaf(const perm_decomp *d, int idx, int *k, double *weight, double *data);
+void perm_decomp_destroy(perm_decomp *d);
 
 /* The k-th prime used by perm_binary_exact (k = 0..4), 0 if out of range. */
 uint64_t perm_binary_prime(int k);

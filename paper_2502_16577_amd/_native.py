@@ -39,6 +39,7 @@ SIGNATURES = [
     ("perm_version", _int, []),
     ("perm_workspace_bytes", _sz, [_int, _int, _i64]),
     ("perm_dense_f64", _int, [_int, _vp, _i64, _vp, _vp, _sz, _vp]),
+    ("perm_dense_f64_ex", _int, [_int, _vp, _i64, _vp, _vp, _vp, _sz, _vp]),
     ("perm_dense_c128", _int, [_int, _vp, _i64, _vp, _vp, _sz, _vp]),
     ("perm_sparse_f64", _int, [_int, _vp, _vp, _vp, _i32, _vp, _vp, _sz, _vp]),
     ("perm_binary_exact", _int, [_int, _vp, _vp, _i32, _int, _vp, _vp, _vp, _vp, _sz, _vp]),
@@ -49,6 +50,12 @@ SIGNATURES = [
     ("perm_batched_workspace_bytes", _sz, [_vp]),
     ("perm_batched", _int, [_vp, _vp, _vp, _vp, _int, _vp, _sz, _vp]),
     ("perm_batched_autotune", _int, [_vp, _vp, _vp, _vp, _vp, _sz, _vp, ctypes.POINTER(ctypes.c_double)]),
+    ("perm_weighted_sum", _int, [_int, _vp, _vp, _vp, _vp]),
+    ("perm_decompose", _int, [_int, _vp, _vp, _vp, _i32, _int, _int, ctypes.POINTER(_vp)]),
+    ("perm_decomp_info", _int, [_vp, ctypes.POINTER(_int), ctypes.POINTER(_int), ctypes.POINTER(_i64),
+                                ctypes.POINTER(_i64)]),
+    ("perm_decomp_leaf", _int, [_vp, _int, ctypes.POINTER(_int), ctypes.POINTER(ctypes.c_double), _vp]),
+    ("perm_decomp_destroy", None, [_vp]),
     ("perm_batched_plan_info", _int, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_int), ctypes.POINTER(_i64)]),
 ]
 

@@ -56,6 +56,38 @@ def perm_dense_f64(A: torch.Tensor, out: torch.Tensor | None = None, ws=None) ->
     return out
 
 
+class PermOptions(ctypes.Structure):
+    """perm_options of include/perm.h."""
+    _fields_ = [("accumulation", ctypes.c_int), ("log2_reseed", ctypes.c_int),
+                ("max_steps_per_launch", ctypes.c_int64)]
+
+
+ACC_TWOSUM = 0
+ACC_PLAIN = 1
+ACC_KAHAN = 2
+
+
+def perm_dense_f64_ex(A: torch.Tensor, accumulation: int = ACC_TWOSUM, log2_reseed: int = 0,
+                      max_steps_per_launch: int = 0, out: torch.Tensor | None = None, ws=None):
+    """perm_dense_f64 with options: accumulation ACC_TWOSUM (default) or
+    ACC_PLAIN (the paper's plain-double "DD" variant), the exact re-seed
+    interval 2^log2_reseed (0 = default) and the longest single launch.
+    ACC_KAHAN selects Kahan-compensated lane sums (the paper's "Kahan")."""
+    _check_square(A)
+    if A.dtype != torch.float64:
+        raise TypeError("float64 expected")
+    n = A.shape[0]
+    if out is None:
+        out = torch.empty((), dtype=torch.float64, device=A.device)
+    ws, need = _workspace(N.KIND_DENSE_F64, n, 0, A.device, ws)
+    opt = PermOptions(accumulation, log2_reseed, max_steps_per_launch)
+    st = N.lib().perm_dense_f64_ex(n, A.data_ptr() if n else None, A.stride(0) if n else 0,
+                                   ctypes.byref(opt), out.data_ptr(), ws.data_ptr(), need,
+                                   _stream(A.device))
+    N.check(st, "perm_dense_f64_ex")
+    return out
+
+
 def perm_dense_c128(A: torch.Tensor, out: torch.Tensor | None = None, ws=None) -> torch.Tensor:
     """Permanent of a dense complex128 CUDA matrix; returns a 0-d device tensor."""
     _check_square(A)
@@ -260,3 +292,75 @@ class BatchedPlan:
         N.check(N.lib().perm_batched_plan_info(self._h, ctypes.byref(ni), ctypes.byref(lc),
                                                ctypes.byref(gs)), "perm_batched_plan_info")
         return {"items": ni.value, "log2_chunk": lc.value, "grid_small": gs.value}
+
+
+DECOMP_DM = 1
+DECOMP_FM = 2
+
+
+def decompose(n: int, col_ptr, row_idx, vals, flags: int = DECOMP_DM | DECOMP_FM,
+              min_leaf: int = 0):
+    """Section 4 preprocessing on the host (no GPU work).
+
+    Returns (leaves, removed) with leaves = [(weight, k x k float64 array)]:
+    perm(A) = sum weight * perm(leaf); an empty list means perm = 0."""
+    col_ptr = np.ascontiguousarray(col_ptr, dtype=np.int32)
+    row_idx = np.ascontiguousarray(row_idx, dtype=np.int32)
+    vals = np.ascontiguousarray(vals, dtype=np.float64)
+    h = ctypes.c_void_p()
+    L = N.lib()
+    N.check(L.perm_decompose(n, col_ptr.ctypes.data, row_idx.ctypes.data if row_idx.size else None,
+                             vals.ctypes.data if vals.size else None, int(row_idx.size), flags,
+                             min_leaf, ctypes.byref(h)), "perm_decompose")
+    try:
+        cnt, mx = ctypes.c_int(), ctypes.c_int()
+        tot, rem = ctypes.c_int64(), ctypes.c_int64()
+        N.check(L.perm_decomp_info(h, ctypes.byref(cnt), ctypes.byref(mx), ctypes.byref(tot),
+                                   ctypes.byref(rem)), "perm_decomp_info")
+        leaves = []
+        for i in range(cnt.value):
+            k, w = ctypes.c_int(), ctypes.c_double()
+            N.check(L.perm_decomp_leaf(h, i, ctypes.byref(k), ctypes.byref(w), None),
+                    "perm_decomp_leaf")
+            m = np.zeros((k.value, k.value))
+            N.check(L.perm_decomp_leaf(h, i, None, None, m.ctypes.data), "perm_decomp_leaf")
+            leaves.append((w.value, m))
+        return leaves, rem.value
+    finally:
+        L.perm_decomp_destroy(h)
+
+
+def perm_sparse_decomp(n: int, col_ptr, row_idx, vals, flags: int = DECOMP_DM | DECOMP_FM,
+                       device="cuda:0"):
+    """perm of a sparse real matrix by the Section 4 pipeline: host
+    decomposition into weighted leaves, one batched GPU launch over the
+    leaves, and a double-double weighted sum on the GPU.  Returns a 0-d
+    float64 device tensor."""
+    device = torch.device(device)
+    leaves, _ = decompose(n, col_ptr, row_idx, vals, flags)
+    out = torch.zeros((), dtype=torch.complex128, device=device)
+    if not leaves:
+        return out.real.clone()
+    from .workloads import pack
+    small = [i for i, (_, m) in enumerate(leaves) if m.shape[0] <= 32]
+    big = [i for i, (_, m) in enumerate(leaves) if m.shape[0] > 32]
+    order = small + big
+    perms = torch.zeros(len(leaves), dtype=torch.complex128, device=device)
+    keep = []
+    if small:
+        ks, offs, data = pack([leaves[i][1].astype(np.complex128) for i in small])
+        plan = BatchedPlan(ks, offs, want_grad=False, device=device)
+        d = torch.from_numpy(data).to(device)
+        plan.run(d, out=perms[:len(small)], use_graph=False)
+        keep += [plan, d]
+    if big:  # orders above the batched limit: one dense launch each
+        pv = perms.view(torch.float64)
+        for t, i in enumerate(big):
+            A = torch.from_numpy(np.ascontiguousarray(leaves[i][1])).to(device)
+            perm_dense_f64(A, out=pv[2 * (len(small) + t)])
+            keep.append(A)
+    w = torch.tensor([leaves[i][0] for i in order], dtype=torch.float64, device=device)
+    N.check(N.lib().perm_weighted_sum(len(leaves), w.data_ptr(), perms.data_ptr(), out.data_ptr(),
+                                      _stream(device)), "perm_weighted_sum")
+    torch.cuda.current_stream(device).synchronize()  # keep plan / weights alive until done
+    return out.real.clone()

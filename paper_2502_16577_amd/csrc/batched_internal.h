@@ -58,4 +58,8 @@ int launch_batched_forked(const BatchLaunch &L, hipStream_t stream,
                           const hipStream_t side[kBatchGroups], hipEvent_t fork,
                           const hipEvent_t join[kBatchGroups]);
 
+// out = sum_m wts[m] * perms[m] (double-double, fixed order).
+int launch_weighted_sum(int count, const double *wts, const perm_c128 *perms, perm_c128 *out,
+                        hipStream_t stream);
+
 }  // namespace perm

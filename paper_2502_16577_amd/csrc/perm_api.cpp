@@ -106,6 +106,9 @@ uint64_t host_prime(int k) { return (uint64_t(1) << 61) - kPrimeCHost[k]; }
 
 using namespace perm;
 
+static_assert(kAccTwoSum == PERM_ACC_TWOSUM && kAccPlain == PERM_ACC_PLAIN && kAccKahan == PERM_ACC_KAHAN,
+              "accumulation modes must match the ABI");
+
 namespace {
 
 bool valid_n(int n) { return n >= 0 && n <= PERM_MAX_N; }
@@ -220,6 +223,28 @@ int perm_dense_f64(int n, const double *A, int64_t lda, double *out, void *ws, s
                             static_cast<hipStream_t>(stream));
 }
 
+int perm_dense_f64_ex(int n, const double *A, int64_t lda, const perm_options *opt, double *out,
+                      void *ws, size_t ws_bytes, void *stream)
+{
+    if (!valid_n(n) || !out) return PERM_EINVAL;
+    if (n > 0 && (!A || lda < n)) return PERM_EINVAL;
+    SweepOptions o = default_sweep_options(n);
+    if (opt) {
+        if (opt->accumulation != PERM_ACC_TWOSUM && opt->accumulation != PERM_ACC_PLAIN &&
+            opt->accumulation != PERM_ACC_KAHAN)
+            return PERM_EINVAL;
+        if (opt->log2_reseed < 0 || opt->log2_reseed > 62 || opt->max_steps_per_launch < 0)
+            return PERM_EINVAL;
+        o.accumulation = opt->accumulation;
+        if (opt->log2_reseed > 0) o.log2_reseed = opt->log2_reseed;
+        if (opt->max_steps_per_launch > 0) o.max_steps_per_launch = opt->max_steps_per_launch;
+    }
+    const int w = check_ws(ws, ws_bytes, perm_workspace_bytes(PERM_KIND_DENSE_F64, n, 0));
+    if (w != PERM_OK) return w;
+    return launch_dense_f64_opt(n, A, lda, out, o, static_cast<char *>(ws),
+                                static_cast<hipStream_t>(stream));
+}
+
 int perm_dense_c128(int n, const perm_c128 *A, int64_t lda, perm_c128 *out, void *ws,
                     size_t ws_bytes, void *stream)
 {
@@ -298,6 +323,60 @@ int perm_binary_exact(int n, const int32_t *col_ptr, const int32_t *row_idx, int
     const int w = check_ws(ws, ws_bytes, L.total);
     if (w != PERM_OK) return w;
 
+    // Zero-block skipping plan (the permanent is invariant under row and
+    // column permutations): columns by ascending count, so the fast-flipping
+    // low columns touch few rows and the densest column is the never-flipped
+    // last one; then rows with no nonzero in columns < b first.
+    int skip_b = 0, nfrozen = 0;
+    if (n > 12) {
+        std::vector<int> col(n);
+        for (int j = 0; j < n; ++j) col[j] = j;
+        std::stable_sort(col.begin(), col.end(), [&](int x, int y) { return csum[x] < csum[y]; });
+        // probability that y_i = 0 for a random subset (binomial count of the
+        // row's flippable nonzeros hitting exactly half the row count)
+        std::vector<double> q(n, 0.0);
+        for (int i = 0; i < n; ++i) {
+            const int last = dense[size_t(i) * n + col[n - 1]] != 0.0;
+            const int rr = rsum[i] - last;
+            const int t = rsum[i] / 2 - last;
+            if (rsum[i] % 2 == 0 && t >= 0 && t <= rr)
+                q[i] = std::exp(std::lgamma(rr + 1.0) - std::lgamma(t + 1.0) - std::lgamma(rr - t + 1.0) -
+                                rr * std::log(2.0));
+        }
+        const double step_cost = 2.0 * n + 5.0;
+        double best = step_cost;
+        for (int b = 1; b <= std::min(plan.log2_chunk, 10); ++b) {
+            double alive = 1.0;  // P(a lane's block is not provably zero)
+            for (int i = 0; i < n; ++i) {
+                bool frozen = true;
+                for (int j = 0; j < b && frozen; ++j) frozen = dense[size_t(i) * n + col[j]] == 0.0;
+                if (frozen) alive *= 1.0 - q[i];
+            }
+            const double p_skip = std::pow(1.0 - alive, 64.0);
+            const double B = double(1 << b);
+            const double cost = (1.5 * n + p_skip * 2.0 * n + (1.0 - p_skip) * B * step_cost) / B;
+            if (cost < 0.8 * best) {
+                best = cost;
+                skip_b = b;
+            }
+        }
+        std::vector<int> row(n);
+        for (int i = 0; i < n; ++i) row[i] = i;
+        if (skip_b > 0) {
+            auto frozen = [&](int i) {
+                for (int j = 0; j < skip_b; ++j)
+                    if (dense[size_t(i) * n + col[j]] != 0.0) return false;
+                return true;
+            };
+            std::stable_partition(row.begin(), row.end(), frozen);
+            for (int i = 0; i < n; ++i) nfrozen += frozen(i);
+        }
+        std::vector<double> perm_dense(size_t(n) * n);
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) perm_dense[size_t(i) * n + j] = dense[size_t(row[i]) * n + col[j]];
+        dense.swap(perm_dense);
+    }
+
     hipStream_t st = static_cast<hipStream_t>(stream);
     char *base = static_cast<char *>(ws);
     if (hipMemcpyAsync(base + L.dense01, dense.data(), dense.size() * sizeof(double),
@@ -305,7 +384,7 @@ int perm_binary_exact(int n, const int32_t *col_ptr, const int32_t *row_idx, int
         return PERM_EHIP;
     uint64_t *res_dev = reinterpret_cast<uint64_t *>(base + L.residues);
     const int rc = launch_binary_residues(n, reinterpret_cast<const double *>(base + L.dense01),
-                                          np, res_dev, base, st);
+                                          np, skip_b, nfrozen, res_dev, base, st);
     if (rc != PERM_OK) return rc;
     uint64_t R[kMaxPrimes] = {0, 0, 0, 0, 0};
     if (hipMemcpyAsync(R, res_dev, sizeof(uint64_t) * np, hipMemcpyDeviceToHost, st) != hipSuccess)

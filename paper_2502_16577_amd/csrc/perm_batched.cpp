@@ -310,6 +310,13 @@ int perm_batched_autotune(perm_plan *plan, const perm_c128 *data, perm_c128 *out
     return rc;
 }
 
+int perm_weighted_sum(int count, const double *weights, const perm_c128 *perms, perm_c128 *out,
+                      void *stream)
+{
+    if (count < 1 || !weights || !perms || !out) return PERM_EINVAL;
+    return launch_weighted_sum(count, weights, perms, out, static_cast<hipStream_t>(stream));
+}
+
 int perm_batched_plan_info(const perm_plan *plan, int64_t *n_items, int *log2_chunk,
                            int64_t *grid_small)
 {

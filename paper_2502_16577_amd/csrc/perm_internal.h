@@ -32,6 +32,23 @@ struct SweepPlan {
 
 SweepPlan plan_sweep(int n, int steps_per_op_hint);
 
+// Run-time options of the dense real sweep.
+constexpr int kAccTwoSum = 0, kAccPlain = 1, kAccKahan = 2;  // lane accumulation modes
+
+struct SweepOptions {
+    int accumulation = kAccTwoSum;                  // kAcc* (same values as PERM_ACC_*)
+    int log2_reseed = 9;                            // exact re-seed every 2^r steps (<= c)
+    int64_t max_steps_per_launch = int64_t(1) << 40;  // split longer sweeps into launches
+};
+
+inline SweepOptions default_sweep_options(int n)
+{
+    SweepOptions o;
+    const SweepPlan p = plan_sweep(n, 0);
+    o.log2_reseed = p.log2_reseed;
+    return o;
+}
+
 // ---------------------------------------------------------------------------
 // Double-double helpers (error-free transformations; require IEEE
 // round-to-nearest and no reassociation, which hipcc gives without
@@ -118,6 +135,8 @@ GradWs grad_ws_layout(int n, int components, int64_t waves);
 // ---------------------------------------------------------------------------
 int launch_dense_f64(int n, const double *A, int64_t lda, double *out, char *ws,
                      hipStream_t stream);
+int launch_dense_f64_opt(int n, const double *A, int64_t lda, double *out, const SweepOptions &o,
+                         char *ws, hipStream_t stream);
 int launch_dense_c128(int n, const perm_c128 *A, int64_t lda, perm_c128 *out, char *ws,
                       hipStream_t stream);
 // Permanent and dperm/dA (row-major n x n, interleaved if complex).
@@ -127,7 +146,9 @@ int launch_grad(int n, bool cplx, const void *A, int64_t lda, void *out_perm, vo
 int launch_grad_or_small(int n, bool cplx, const void *A, int64_t lda, void *out_perm,
                          void *out_grad, bool want_grad, char *ws, hipStream_t stream);
 // Residues R_k = sum_g (-1)^g prod_i y_i(g) mod p_k (k < nprimes) into residues_dev.
-int launch_binary_residues(int n, const double *dense01, int nprimes, uint64_t *residues_dev,
-                           char *ws, hipStream_t stream);
+// skip_b > 0 enables exact zero-block skipping with blocks of 2^skip_b steps;
+// rows 0 .. nfrozen-1 must then have no nonzero in columns 0 .. skip_b-1.
+int launch_binary_residues(int n, const double *dense01, int nprimes, int skip_b, int nfrozen,
+                           uint64_t *residues_dev, char *ws, hipStream_t stream);
 
 }  // namespace perm

@@ -143,6 +143,35 @@ __global__ __launch_bounds__(kBlock) void batched_finalize(const BatchMatDev *__
     }
 }
 
+// sum_m w_m perm_m in double-double, fixed order, one block.
+__global__ __launch_bounds__(kBlock) void weighted_sum(int count, const double *__restrict__ wts,
+                                                       const perm_c128 *__restrict__ perms,
+                                                       perm_c128 *__restrict__ out)
+{
+    __shared__ dd red[kWavesPerBlock];
+    for (int q = 0; q < 2; ++q) {
+        dd acc = dd{0.0, 0.0};
+        for (int m = threadIdx.x; m < count; m += kBlock) {
+            const double v = q == 0 ? perms[m].re : perms[m].im;
+            const double p = wts[m] * v;
+            const double e = __builtin_fma(wts[m], v, -p);  // exact product error
+            acc = dd_add(acc, dd{p, e});
+        }
+        const dd t = block_reduce_dd(acc, red);
+        if (threadIdx.x == 0) {
+            if (q == 0) out->re = t.hi + t.lo;
+            else out->im = t.hi + t.lo;
+        }
+    }
+}
+
+int launch_weighted_sum(int count, const double *wts, const perm_c128 *perms, perm_c128 *out,
+                        hipStream_t stream)
+{
+    hipLaunchKernelGGL(weighted_sum, dim3(1), dim3(kBlock), 0, stream, count, wts, perms, out);
+    return hipGetLastError() == hipSuccess ? PERM_OK : PERM_EHIP;
+}
+
 static void launch_persistent(const BatchLaunch &L, int g, hipStream_t stream)
 {
     if (L.n_items[g] <= 0) return;

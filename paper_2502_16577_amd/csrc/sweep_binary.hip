@@ -161,11 +161,17 @@ __device__ __forceinline__ void drain_entry(const double *__restrict__ q, int sl
     }
 }
 
+// Exact zero-block skipping (skip_b > 0): inside an aligned block of 2^b
+// local steps only columns < b flip, so the first `nfrozen` rows (the host
+// orders rows so that these have no nonzero in columns < b) keep their y for
+// the whole block.  If one of them is zero for every lane of the wave, all
+// 2^b terms of the block are zero and the block reduces to its net effect, a
+// single flip of column b - 1.
 template <int N>
 __global__ __launch_bounds__(kBlock) void sweep_binary(const double *__restrict__ ycol,
                                                        const double *__restrict__ yneg,
                                                        const double *__restrict__ y0, int c,
-                                                       int nprimes,
+                                                       int nprimes, int skip_b, int nfrozen,
                                                        uint64_t *__restrict__ partials)
 {
     constexpr int M = BinGroups<N>::M;
@@ -237,6 +243,7 @@ __global__ __launch_bounds__(kBlock) void sweep_binary(const double *__restrict_
         }
     };
 
+    const uint32_t bmask = skip_b > 0 ? (1u << skip_b) - 1u : 0u;
     for (uint32_t l = 0; l < C; l += 2) {
         if (l != 0) {
             const int j = __builtin_ctz(l);
@@ -244,6 +251,22 @@ __global__ __launch_bounds__(kBlock) void sweep_binary(const double *__restrict_
             const double *a = (add ? ycol : yneg) + j * N;
 #pragma unroll
             for (int i = 0; i < N; ++i) y[i] += a[i];
+        }
+        if (skip_b > 0 && (l & bmask) == 0) {
+            double pf = 1.0;
+#pragma unroll
+            for (int i = 0; i < N; ++i)
+                if (i < nfrozen) pf *= y[i];
+            if (__ballot(pf != 0.0) == 0) {
+                // net effect of the block: column b - 1 flips once (at l + 2^(b-1))
+                const uint32_t lh = l + (1u << (skip_b - 1));
+                const bool add = (gray_low(lh, kb, c) >> (skip_b - 1)) & 1u;
+                const double *a = (add ? ycol : yneg) + (skip_b - 1) * N;
+#pragma unroll
+                for (int i = 0; i < N; ++i) y[i] += a[i];
+                l += bmask - 1u;  // the loop adds 2: next step is the next block's start
+                continue;
+            }
         }
         push_term(false);  // (-1)^g = +1 for even l
         {
@@ -307,14 +330,15 @@ __global__ __launch_bounds__(kBlock) void finalize_residues(const uint64_t *__re
 
 template <int N>
 static void launch_bin_n(const SweepPlan &p, const double *ycol, const double *yneg,
-                         const double *y0, int nprimes, uint64_t *partials, hipStream_t stream)
+                         const double *y0, int nprimes, int skip_b, int nfrozen,
+                         uint64_t *partials, hipStream_t stream)
 {
     hipLaunchKernelGGL(sweep_binary<N>, dim3(unsigned(p.blocks)), dim3(kBlock), 0, stream, ycol,
-                       yneg, y0, p.log2_chunk, nprimes, partials);
+                       yneg, y0, p.log2_chunk, nprimes, skip_b, nfrozen, partials);
 }
 
 using BinLauncher = void (*)(const SweepPlan &, const double *, const double *, const double *,
-                             int, uint64_t *, hipStream_t);
+                             int, int, int, uint64_t *, hipStream_t);
 
 template <int... Ns>
 struct BinTable {
@@ -331,8 +355,8 @@ using BinaryTable =
              34, 35, 36, 37, 38, 39, 40, 41, 42, 43, 44, 45, 46, 47, 48, 49, 50, 51, 52, 53, 54,
              55, 56, 57, 58, 59, 60, 61, 62, 63>;
 
-int launch_binary_residues(int n, const double *dense01, int nprimes, uint64_t *residues_dev,
-                           char *ws, hipStream_t stream)
+int launch_binary_residues(int n, const double *dense01, int nprimes, int skip_b, int nfrozen,
+                           uint64_t *residues_dev, char *ws, hipStream_t stream)
 {
     const SweepPlan p = plan_sweep(n, 0);
     const BinaryWs L = binary_ws_layout(n, p.blocks);
@@ -348,7 +372,8 @@ int launch_binary_residues(int n, const double *dense01, int nprimes, uint64_t *
     } else {
         BinLauncher f = BinaryTable::get(n);
         if (!f) return PERM_EUNSUPPORTED;
-        f(p, ycol, yneg, y0, nprimes, partials, stream);
+        f(p, ycol, yneg, y0, nprimes, skip_b > p.log2_chunk ? 0 : skip_b, nfrozen, partials,
+          stream);
         nparts = p.blocks;
     }
     hipLaunchKernelGGL(finalize_residues, dim3(1), dim3(kBlock), 0, stream, partials, nparts,

@@ -82,15 +82,21 @@ __device__ __forceinline__ void reseed(double (&x)[N], const double *__restrict_
     }
 }
 
-template <int N>
+// ACC: how a lane accumulates its terms -- kAccTwoSum (two-sum: the lane
+// partial is a double-double, the paper's "DQ" of Table 3), kAccKahan (Kahan
+// compensation, the paper's "Kahan"), kAccPlain (plain doubles, the paper's
+// "DD").  block_offset lets a long sweep run as several launches over
+// consecutive block ranges.
+template <int N, int ACC>
 __global__ __launch_bounds__(kBlock) void sweep_dense_f64(const double *__restrict__ acol,
                                                           const double *__restrict__ aneg,
                                                           const double *__restrict__ x0,
-                                                          dd *__restrict__ partials, int c, int r)
+                                                          dd *__restrict__ partials, int c, int r,
+                                                          uint32_t block_offset)
 {
     __shared__ dd red[kWavesPerBlock];
     const uint32_t lane = threadIdx.x & 63u;
-    const uint64_t wave = uniform_wave_index();
+    const uint64_t wave = uniform_wave_index() + uint64_t(block_offset) * kWavesPerBlock;
     const uint64_t K = lane_chunk_index(wave, lane);
     const uint32_t kb = uint32_t(wave & 1u);
     const uint64_t g0 = K << c;
@@ -115,22 +121,51 @@ __global__ __launch_bounds__(kBlock) void sweep_dense_f64(const double *__restri
         add_column<N>(x, add0 ? acol : aneg);
         const double t_odd = product4<N>(x);
         // (-1)^g = (-1)^l since every chunk starts at an even g
-        acc_add(s, e, t_even - t_odd);
+        if constexpr (ACC == kAccTwoSum) {
+            acc_add(s, e, t_even - t_odd);
+        } else if constexpr (ACC == kAccKahan) {
+            const double y = (t_even - t_odd) - e;  // e holds the running compensation
+            const double t = s + y;
+            e = (t - s) - y;
+            s = t;
+        } else {
+            s += t_even - t_odd;
+        }
     }
-    const dd t = block_reduce_dd(dd{s, e}, red);
-    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+    // Kahan's e is the negated lost low part
+    const dd t = block_reduce_dd(ACC == kAccKahan ? dd{s, -e} : dd{s, e}, red);
+    if (threadIdx.x == 0) partials[blockIdx.x + block_offset] = t;
 }
 
+// Launches the sweep as consecutive block ranges of at most
+// max_steps_per_launch subset-steps each (one launch for the usual sizes).
 template <int N>
-static void launch_sweep_n(const SweepPlan &p, const double *acol, const double *aneg,
-                           const double *x0, dd *partials, hipStream_t stream)
+static void launch_sweep_n(const SweepPlan &p, const SweepOptions &o, const double *acol,
+                           const double *aneg, const double *x0, dd *partials,
+                           hipStream_t stream)
 {
-    hipLaunchKernelGGL(sweep_dense_f64<N>, dim3(unsigned(p.blocks)), dim3(kBlock), 0, stream,
-                       acol, aneg, x0, partials, p.log2_chunk, p.log2_reseed);
+    const int64_t steps_per_block = int64_t(kBlock) << p.log2_chunk;
+    int64_t per = o.max_steps_per_launch / steps_per_block;
+    if (per < 1) per = 1;
+    for (int64_t b0 = 0; b0 < p.blocks; b0 += per) {
+        const int64_t nb = p.blocks - b0 < per ? p.blocks - b0 : per;
+        if (o.accumulation == kAccTwoSum)
+            hipLaunchKernelGGL((sweep_dense_f64<N, kAccTwoSum>), dim3(unsigned(nb)), dim3(kBlock),
+                               0, stream, acol, aneg, x0, partials, p.log2_chunk, o.log2_reseed,
+                               uint32_t(b0));
+        else if (o.accumulation == kAccKahan)
+            hipLaunchKernelGGL((sweep_dense_f64<N, kAccKahan>), dim3(unsigned(nb)), dim3(kBlock),
+                               0, stream, acol, aneg, x0, partials, p.log2_chunk, o.log2_reseed,
+                               uint32_t(b0));
+        else
+            hipLaunchKernelGGL((sweep_dense_f64<N, kAccPlain>), dim3(unsigned(nb)), dim3(kBlock),
+                               0, stream, acol, aneg, x0, partials, p.log2_chunk, o.log2_reseed,
+                               uint32_t(b0));
+    }
 }
 
-using SweepLauncher = void (*)(const SweepPlan &, const double *, const double *, const double *,
-                               dd *, hipStream_t);
+using SweepLauncher = void (*)(const SweepPlan &, const SweepOptions &, const double *,
+                               const double *, const double *, dd *, hipStream_t);
 
 template <int... Ns>
 struct SweepTable {
@@ -152,6 +187,12 @@ __global__ void write_one_f64(double *out) { out[0] = 1.0; }
 int launch_dense_f64(int n, const double *A, int64_t lda, double *out, char *ws,
                      hipStream_t stream)
 {
+    return launch_dense_f64_opt(n, A, lda, out, default_sweep_options(n), ws, stream);
+}
+
+int launch_dense_f64_opt(int n, const double *A, int64_t lda, double *out, const SweepOptions &o,
+                         char *ws, hipStream_t stream)
+{
     if (n == 0) {
         hipLaunchKernelGGL(write_one_f64, dim3(1), dim3(1), 0, stream, out);
         return hipGetLastError() == hipSuccess ? PERM_OK : PERM_EHIP;
@@ -169,7 +210,9 @@ int launch_dense_f64(int n, const double *A, int64_t lda, double *out, char *ws,
     {
         SweepLauncher f = DenseF64Table::get(n);
         if (!f) return PERM_EUNSUPPORTED;
-        f(p, acol, aneg, x0, partials, stream);
+        SweepOptions oo = o;
+        if (oo.log2_reseed < 1 || oo.log2_reseed > p.log2_chunk) oo.log2_reseed = p.log2_chunk;
+        f(p, oo, acol, aneg, x0, partials, stream);
     }
     const double scale = (n & 1) ? 2.0 : -2.0;  // 2 (-1)^(n-1)
     hipLaunchKernelGGL(finalize_partials, dim3(1), dim3(kBlock), 0, stream, partials, nparts, 1,

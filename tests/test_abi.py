@@ -150,3 +150,18 @@ def test_batched_plan_errors_and_workspace():
     assert lib.perm_batched(h, FAKE, FAKE, FAKE, 1, FAKE, nb - 1, None) == N.PERM_EWORKSPACE
     assert lib.perm_batched(h, FAKE, FAKE, None, 1, FAKE, nb, None) == N.PERM_EINVAL
     lib.perm_plan_destroy(h)
+
+
+def test_dense_ex_option_errors():
+    import ctypes
+    from paper_2502_16577_amd.api import PermOptions
+    lib = N.lib()
+    big = 1 << 30
+    bad = PermOptions(7, 0, 0)
+    assert lib.perm_dense_f64_ex(20, FAKE, 20, ctypes.byref(bad), FAKE, FAKE, big, None) == N.PERM_EINVAL
+    bad = PermOptions(0, -1, 0)
+    assert lib.perm_dense_f64_ex(20, FAKE, 20, ctypes.byref(bad), FAKE, FAKE, big, None) == N.PERM_EINVAL
+    bad = PermOptions(0, 0, -5)
+    assert lib.perm_dense_f64_ex(20, FAKE, 20, ctypes.byref(bad), FAKE, FAKE, big, None) == N.PERM_EINVAL
+    ok = PermOptions(1, 4, 1 << 20)
+    assert lib.perm_dense_f64_ex(20, FAKE, 20, ctypes.byref(ok), FAKE, None, 0, None) == N.PERM_EWORKSPACE

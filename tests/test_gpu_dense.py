@@ -124,3 +124,27 @@ def test_full_size_haar30():
     got = complex(api.perm(torch.from_numpy(a).to(DEV)).cpu().item())
     assert abs(got - want) <= 1e-10 * g["abs_perm"]
     assert abs(got - want) <= 1e-13 * g["abs_sum"], (got, want)
+
+
+def test_options_plain_and_split(oracle):
+    a = W.uniform(26, 91)
+    A = torch.from_numpy(a).to(DEV)
+    want = oracle.ryser(a)
+    ref = api.perm_dense_f64(A).item()
+    # splitting the sweep into many launches does not change a single bit
+    split = api.perm_dense_f64_ex(A, max_steps_per_launch=1 << 18).item()
+    assert split == ref
+    # plain (paper "DD") accumulation and other re-seed intervals stay within tolerance
+    for acc in (api.ACC_TWOSUM, api.ACC_PLAIN, api.ACC_KAHAN):
+        for r in (0, 3, 7, 62):
+            v = api.perm_dense_f64_ex(A, accumulation=acc, log2_reseed=r).item()
+            assert abs(v - want) <= 1e-10 * abs(want), (acc, r, v, want)
+
+
+@pytest.mark.parametrize("n", [35, 36])
+def test_all_equal_paper_size(n):
+    # Section 5 / Table 3 shapes: all entries 0.91, perm = n! 0.91^n (2^34 and 2^35 steps)
+    a = np.full((n, n), 0.91)
+    exact = math.factorial(n) * 0.91 ** n
+    got = gpu_perm(a)
+    assert abs(got - exact) <= 1e-10 * exact, (n, got, exact, abs(got - exact) / exact)
