@@ -169,8 +169,8 @@ PAPER_TABLE3_GV100 = {35: {"DD": 1.40e-9, "Kahan": 8.78e-12, "DD_s": 1.31, "Kaha
 def paper_tables(sizes):
     """Table 4 shapes (dense U[0,1), one matrix per n) and Table 3 shapes (all
     entries 0.91, perm = n! 0.91^n) on this GPU; one JSON line per row."""
+    import fractions
     import math
-    import numpy as np
     import torch
     from paper_2502_16577_amd import api, workloads
 
@@ -188,7 +188,8 @@ def paper_tables(sizes):
                           "paper_gv100_s": PAPER_TABLE4_GV100_S.get(n),
                           "paper_cpu44_s": PAPER_TABLE4_CPU44_S.get(n)}), flush=True)
         J = torch.full((n, n), 0.91, dtype=torch.float64, device=dev)
-        exact = math.factorial(n) * 0.91 ** n
+        # n! a^n in exact rational arithmetic for the stored double a = fl(0.91)
+        exact = float(math.factorial(n) * fractions.Fraction(0.91) ** n)
         for name, acc in (("twosum", api.ACC_TWOSUM), ("kahan", api.ACC_KAHAN),
                           ("plain", api.ACC_PLAIN)):
             torch.cuda.synchronize()

@@ -103,6 +103,10 @@ typedef struct {
                                       values above the lane's chunk mean once per chunk */
     int64_t max_steps_per_launch;  /* 0 = default (2^40): longer sweeps are split into
                                       several launches over consecutive lane ranges */
+    int log2_lanes;                /* 0 = default (about 2^18 lanes); else the number of
+                                      lanes (one Gray chunk each) as a power of two, clamped
+                                      so that every lane walks at least 4 steps and a block
+                                      of 256 lanes is full */
 } perm_options;
 
 /* perm_dense_f64 with options (opt may be NULL).  PERM_EINVAL for an unknown

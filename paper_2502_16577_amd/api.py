@@ -59,7 +59,7 @@ def perm_dense_f64(A: torch.Tensor, out: torch.Tensor | None = None, ws=None) ->
 class PermOptions(ctypes.Structure):
     """perm_options of include/perm.h."""
     _fields_ = [("accumulation", ctypes.c_int), ("log2_reseed", ctypes.c_int),
-                ("max_steps_per_launch", ctypes.c_int64)]
+                ("max_steps_per_launch", ctypes.c_int64), ("log2_lanes", ctypes.c_int)]
 
 
 ACC_TWOSUM = 0
@@ -68,7 +68,8 @@ ACC_KAHAN = 2
 
 
 def perm_dense_f64_ex(A: torch.Tensor, accumulation: int = ACC_TWOSUM, log2_reseed: int = 0,
-                      max_steps_per_launch: int = 0, out: torch.Tensor | None = None, ws=None):
+                      max_steps_per_launch: int = 0, log2_lanes: int = 0,
+                      out: torch.Tensor | None = None, ws=None):
     """perm_dense_f64 with options: accumulation ACC_TWOSUM (default) or
     ACC_PLAIN (the paper's plain-double "DD" variant), the exact re-seed
     interval 2^log2_reseed (0 = default) and the longest single launch.
@@ -80,7 +81,7 @@ def perm_dense_f64_ex(A: torch.Tensor, accumulation: int = ACC_TWOSUM, log2_rese
     if out is None:
         out = torch.empty((), dtype=torch.float64, device=A.device)
     ws, need = _workspace(N.KIND_DENSE_F64, n, 0, A.device, ws)
-    opt = PermOptions(accumulation, log2_reseed, max_steps_per_launch)
+    opt = PermOptions(accumulation, log2_reseed, max_steps_per_launch, log2_lanes)
     st = N.lib().perm_dense_f64_ex(n, A.data_ptr() if n else None, A.stride(0) if n else 0,
                                    ctypes.byref(opt), out.data_ptr(), ws.data_ptr(), need,
                                    _stream(A.device))

@@ -191,8 +191,7 @@ size_t perm_workspace_bytes(int kind, int n, int64_t m)
     case PERM_KIND_DENSE_C128: {
         const int comps = kind == PERM_KIND_DENSE_C128 ? 2 : 1;
         if (n <= kSmallN) return grad_ws_layout(n, comps, plan_grad(n).waves).total;
-        const SweepPlan p = plan_sweep(n, 0);
-        return dense_ws_layout(n, comps, p.blocks).total;
+        return dense_ws_layout(n, comps, dense_ws_blocks(n)).total;
     }
     case PERM_KIND_SPARSE_F64: {
         return perm_workspace_bytes(PERM_KIND_DENSE_F64, n, 0) +
@@ -233,8 +232,10 @@ int perm_dense_f64_ex(int n, const double *A, int64_t lda, const perm_options *o
         if (opt->accumulation != PERM_ACC_TWOSUM && opt->accumulation != PERM_ACC_PLAIN &&
             opt->accumulation != PERM_ACC_KAHAN)
             return PERM_EINVAL;
-        if (opt->log2_reseed < 0 || opt->log2_reseed > 62 || opt->max_steps_per_launch < 0)
+        if (opt->log2_reseed < 0 || opt->log2_reseed > 62 || opt->max_steps_per_launch < 0 ||
+            opt->log2_lanes < 0 || opt->log2_lanes > 40)
             return PERM_EINVAL;
+        o.log2_lanes = opt->log2_lanes;
         o.accumulation = opt->accumulation;
         if (opt->log2_reseed > 0) o.log2_reseed = opt->log2_reseed;
         if (opt->max_steps_per_launch > 0) o.max_steps_per_launch = opt->max_steps_per_launch;

@@ -39,6 +39,7 @@ struct SweepOptions {
     int accumulation = kAccTwoSum;                  // kAcc* (same values as PERM_ACC_*)
     int log2_reseed = 9;                            // exact re-seed every 2^r steps (<= c)
     int64_t max_steps_per_launch = int64_t(1) << 40;  // split longer sweeps into launches
+    int log2_lanes = 0;                             // 0 = plan_sweep's choice
 };
 
 inline SweepOptions default_sweep_options(int n)
@@ -94,6 +95,14 @@ struct DenseWs {
 };
 
 DenseWs dense_ws_layout(int n, int components, int64_t blocks);
+
+// Block partials a dense workspace holds: the default plan's blocks, and at
+// least 1024 (2^18 lanes) so perm_dense_f64_ex may choose other lane counts.
+inline int64_t dense_ws_blocks(int n)
+{
+    const int64_t b = plan_sweep(n, 0).blocks;
+    return b > 1024 ? b : 1024;
+}
 
 struct BinaryWs {
     size_t dense01 = 0;   // n*n doubles, the 0/1 pattern row-major (staged from the host CSC)

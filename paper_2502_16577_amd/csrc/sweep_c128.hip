@@ -183,7 +183,7 @@ int launch_dense_c128(int n, const perm_c128 *A, int64_t lda, perm_c128 *out, ch
         return hipGetLastError() == hipSuccess ? PERM_OK : PERM_EHIP;
     }
     const SweepPlan p = plan_sweep(n, 0);
-    const DenseWs L = dense_ws_layout(n, 2, p.blocks);
+    const DenseWs L = dense_ws_layout(n, 2, dense_ws_blocks(n));
     double *acol = reinterpret_cast<double *>(ws + L.acol);
     double *aneg = reinterpret_cast<double *>(ws + L.aneg);
     double *x0 = reinterpret_cast<double *>(ws + L.x0);

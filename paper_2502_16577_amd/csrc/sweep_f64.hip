@@ -14,6 +14,9 @@
 // the flipped column j = ctz(l) and its sign are wave-uniform at every step,
 // so the column is fetched with scalar loads into SGPRs and feeds v_add_f64
 // directly: no LDS traffic and no per-lane addressing in the hot loop.
+#include <algorithm>
+#include <cmath>
+
 #include "sweep_common.h"
 
 namespace perm {
@@ -193,12 +196,27 @@ int launch_dense_f64(int n, const double *A, int64_t lda, double *out, char *ws,
 int launch_dense_f64_opt(int n, const double *A, int64_t lda, double *out, const SweepOptions &o,
                          char *ws, hipStream_t stream)
 {
+    // The workspace holds block partials for max(default, 2^18 lanes); other
+    // lane counts are clamped to that.
     if (n == 0) {
         hipLaunchKernelGGL(write_one_f64, dim3(1), dim3(1), 0, stream, out);
         return hipGetLastError() == hipSuccess ? PERM_OK : PERM_EHIP;
     }
-    const SweepPlan p = plan_sweep(n, 0);
-    const DenseWs L = dense_ws_layout(n, 1, p.blocks);
+    SweepPlan p = plan_sweep(n, 0);
+    if (o.log2_lanes > 0 && n > kSmallN) {
+        const int total = n - 1;
+        int ll = o.log2_lanes;
+        const int max_ll = std::max(total - 2, 8);
+        if (ll > max_ll) ll = max_ll;
+        if (ll < 8) ll = 8;                       // one full block of 256 lanes
+        const int def_ll = int(std::log2(double(p.lanes)));
+        if (ll > std::max(18, def_ll)) ll = std::max(18, def_ll);
+        p.log2_chunk = total - ll;
+        p.lanes = int64_t(1) << ll;
+        p.blocks = p.lanes / kBlock;
+        if (p.log2_reseed > p.log2_chunk) p.log2_reseed = p.log2_chunk;
+    }
+    const DenseWs L = dense_ws_layout(n, 1, dense_ws_blocks(n));
     double *acol = reinterpret_cast<double *>(ws + L.acol);
     double *aneg = reinterpret_cast<double *>(ws + L.aneg);
     double *x0 = reinterpret_cast<double *>(ws + L.x0);

@@ -157,11 +157,13 @@ def test_dense_ex_option_errors():
     from paper_2502_16577_amd.api import PermOptions
     lib = N.lib()
     big = 1 << 30
-    bad = PermOptions(7, 0, 0)
+    bad = PermOptions(7, 0, 0, 0)
     assert lib.perm_dense_f64_ex(20, FAKE, 20, ctypes.byref(bad), FAKE, FAKE, big, None) == N.PERM_EINVAL
-    bad = PermOptions(0, -1, 0)
+    bad = PermOptions(0, -1, 0, 0)
     assert lib.perm_dense_f64_ex(20, FAKE, 20, ctypes.byref(bad), FAKE, FAKE, big, None) == N.PERM_EINVAL
-    bad = PermOptions(0, 0, -5)
+    bad = PermOptions(0, 0, -5, 0)
     assert lib.perm_dense_f64_ex(20, FAKE, 20, ctypes.byref(bad), FAKE, FAKE, big, None) == N.PERM_EINVAL
-    ok = PermOptions(1, 4, 1 << 20)
+    bad = PermOptions(0, 0, 0, -1)
+    assert lib.perm_dense_f64_ex(20, FAKE, 20, ctypes.byref(bad), FAKE, FAKE, big, None) == N.PERM_EINVAL
+    ok = PermOptions(1, 4, 1 << 20, 12)
     assert lib.perm_dense_f64_ex(20, FAKE, 20, ctypes.byref(ok), FAKE, None, 0, None) == N.PERM_EWORKSPACE

@@ -134,6 +134,9 @@ def test_options_plain_and_split(oracle):
     # splitting the sweep into many launches does not change a single bit
     split = api.perm_dense_f64_ex(A, max_steps_per_launch=1 << 18).item()
     assert split == ref
+    for ll in (8, 12, 16, 23):
+        v = api.perm_dense_f64_ex(A, log2_lanes=ll).item()
+        assert abs(v - want) <= 1e-10 * abs(want), (ll, v, want)
     # plain (paper "DD") accumulation and other re-seed intervals stay within tolerance
     for acc in (api.ACC_TWOSUM, api.ACC_PLAIN, api.ACC_KAHAN):
         for r in (0, 3, 7, 62):
