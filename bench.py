@@ -39,8 +39,8 @@ PEAK_FMA_TFLOPS = 78.6                           # published FP64 vector peak (F
 # plain 1 GiB copy (profiles/sweep_dense_f64_n32_u01.md).  Valid only for the
 # kernel source they were measured on; reported as null once it changes.
 COUNTERS_SRC = os.path.join(ROOT, "paper_2502_16577_amd", "csrc", "sweep_f64.hip")
-COUNTERS_SRC_SHA256 = "af1ec4abc621ea97686c7d830e2358ecf6088956e2f2249399d83ec21ca7e5da"
-TRAFFIC_BYTES_PER_LAUNCH = 124 * 1024 * 2.000 + 32 * 1024 * 1.000
+COUNTERS_SRC_SHA256 = "4cf2ce9695ee0e6196cd8c26bad56ab889c3636e56637db083a55de6695f85b1"
+TRAFFIC_BYTES_PER_LAUNCH = 186 * 1024 * 2.000 + 32 * 1024 * 1.000
 
 
 def traffic_bytes():

@@ -85,7 +85,21 @@ __device__ __forceinline__ void reseed(double (&x)[N], const double *__restrict_
     }
 }
 
-// ACC: how a lane accumulates its terms -- kAccTwoSum (two-sum: the lane
+// One lane walks its chunk in blocks of 2^U steps.  In a block starting at
+// l (a multiple of 2^U) only step l flips a column chosen at run time (ctz(l),
+// or an exact re-seed); step l + m, 0 < m < 2^U, flips column ctz(m), and its
+// sign -- bit ctz(m) of the Gray code after the step, i.e. bit ctz(m) + 1 of
+// l + m inverted -- is fixed by m alone, except for m = 2^(U-1) where it is
+// bit U of l.  So 2^U - 1 of every 2^U flips read a column at a constant
+// address with a constant sign, and the 2^U signed terms are summed in a
+// short tree before one compensated update of the lane partial.
+// Requires c > U (so bit U of g lies inside the chunk); re-seeds happen at
+// block starts, so the effective re-seed interval is at least 2^U.  U = 4
+// (16-step blocks) where the plan's chunks allow it (n >= 14), else 3.
+template <int N>
+constexpr int dense_unroll() { return N >= 14 ? 4 : 3; }
+
+// ACC: how a lane accumulates the block sums -- kAccTwoSum (two-sum: the lane
 // partial is a double-double, the paper's "DQ" of Table 3), kAccKahan (Kahan
 // compensation, the paper's "Kahan"), kAccPlain (plain doubles, the paper's
 // "DD").  block_offset lets a long sweep run as several launches over
@@ -97,6 +111,8 @@ __global__ __launch_bounds__(kBlock) void sweep_dense_f64(const double *__restri
                                                           dd *__restrict__ partials, int c, int r,
                                                           uint32_t block_offset)
 {
+    constexpr int U = dense_unroll<N>();
+    constexpr uint32_t B = 1u << U;
     __shared__ dd red[kWavesPerBlock];
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t wave = uniform_wave_index() + uint64_t(block_offset) * kWavesPerBlock;
@@ -109,8 +125,8 @@ __global__ __launch_bounds__(kBlock) void sweep_dense_f64(const double *__restri
 
     double x[N];
     double s = 0.0, e = 0.0;
-    for (uint32_t l = 0; l < C; l += 2) {
-        // even step l: re-seed exactly, or flip column ctz(l)
+    for (uint32_t l = 0; l < C; l += B) {
+        // step l: re-seed exactly, or flip column ctz(l)
         if ((l & rmask) == 0) {
             reseed<N>(x, acol, x0, hbits, gray_low(l, kb, c), c);
         } else {
@@ -118,21 +134,37 @@ __global__ __launch_bounds__(kBlock) void sweep_dense_f64(const double *__restri
             const bool add = (gray_low(l, kb, c) >> j) & 1u;
             add_column<N>(x, (add ? acol : aneg) + j * N);
         }
-        const double t_even = product4<N>(x);
-        // odd step l + 1: always flips column 0
-        const bool add0 = gray_low(l + 1, kb, c) & 1u;
-        add_column<N>(x, add0 ? acol : aneg);
-        const double t_odd = product4<N>(x);
-        // (-1)^g = (-1)^l since every chunk starts at an even g
+        double t[B];
+        t[0] = product4<N>(x);
+#pragma unroll
+        for (uint32_t m = 1; m < B; ++m) {
+            const int j = __builtin_ctz(m);
+            const bool neg = (j + 1 < U) ? ((m >> (j + 1)) & 1u) : ((l >> U) & 1u);
+            // An offset the compiler cannot see through, fresh at every step:
+            // otherwise it merges or hoists these constant-address column
+            // loads and keeps whole columns live in SGPRs, which spills.
+            uint32_t zero = 0;
+            asm volatile("" : "+s"(zero));
+            add_column<N>(x, (neg ? aneg : acol) + j * N + zero);
+            t[m] = product4<N>(x);
+        }
+        // (-1)^g = (-1)^m since l is even
+#pragma unroll
+        for (uint32_t m = 0; m < B; m += 2) t[m] -= t[m + 1];
+#pragma unroll
+        for (uint32_t w = 4; w <= B; w *= 2)
+#pragma unroll
+            for (uint32_t m = 0; m < B; m += w) t[m] += t[m + w / 2];
+        const double v = t[0];
         if constexpr (ACC == kAccTwoSum) {
-            acc_add(s, e, t_even - t_odd);
+            acc_add(s, e, v);
         } else if constexpr (ACC == kAccKahan) {
-            const double y = (t_even - t_odd) - e;  // e holds the running compensation
-            const double t = s + y;
-            e = (t - s) - y;
-            s = t;
+            const double y = v - e;  // e holds the running compensation
+            const double u = s + y;
+            e = (u - s) - y;
+            s = u;
         } else {
-            s += t_even - t_odd;
+            s += v;
         }
     }
     // Kahan's e is the negated lost low part
@@ -206,7 +238,8 @@ int launch_dense_f64_opt(int n, const double *A, int64_t lda, double *out, const
     if (o.log2_lanes > 0 && n > kSmallN) {
         const int total = n - 1;
         int ll = o.log2_lanes;
-        const int max_ll = std::max(total - 2, 8);
+        const int unroll = n >= 14 ? 4 : 3;                    // dense_unroll<n>()
+        const int max_ll = std::max(total - 1 - unroll, 8);   // c > U
         if (ll > max_ll) ll = max_ll;
         if (ll < 8) ll = 8;                       // one full block of 256 lanes
         const int def_ll = int(std::log2(double(p.lanes)));
@@ -228,6 +261,7 @@ int launch_dense_f64_opt(int n, const double *A, int64_t lda, double *out, const
     {
         SweepLauncher f = DenseF64Table::get(n);
         if (!f) return PERM_EUNSUPPORTED;
+        if (p.log2_chunk <= (n >= 14 ? 4 : 3)) return PERM_EUNSUPPORTED;  // the block walk needs c > U
         SweepOptions oo = o;
         if (oo.log2_reseed < 1 || oo.log2_reseed > p.log2_chunk) oo.log2_reseed = p.log2_chunk;
         f(p, oo, acol, aneg, x0, partials, stream);
