@@ -136,7 +136,8 @@ def bench_batched(reps: int = 5):
         per_k[k] = (time.perf_counter() - t0) * 1e3
     plain_ms = float(sum(per_k[int(k)] for k in ks))
 
-    # MFMA work of the contraction: 2 real GEMMs (Re, Im of L) x 2 k^2 flops per subset
+    # GEMM-equivalent work of the contraction G += V tau^T: 2 real GEMMs (Re, Im
+    # of V) x 2 k^2 flops per subset; the windowed kernel issues 1/16 of it on MFMA
     mfma_flops = float(sum((2 ** (int(k) - 1)) * 4 * int(k) ** 2 for k in ks))
     return {
         "workload": "4096 complex128 k x k submatrices, k ~ U{8..24}, rows/cols drawn with "
@@ -153,8 +154,105 @@ def bench_batched(reps: int = 5):
                                "k^2 minors (1 + k^2 launches), scaled by the order histogram",
         "speedup_vs_plain_solver": plain_ms / batch_ms,
         "speedup_vs_per_matrix_perm_grad": per_grad_ms / batch_ms,
-        "mfma_algorithmic_tflops": mfma_flops / (batch_ms * 1e-3) / 1e12,
+        "gemm_equivalent_tflops": mfma_flops / (batch_ms * 1e-3) / 1e12,
     }
+
+
+def _timed(fn, reps, stream):
+    """Average HIP-event milliseconds of fn() over reps calls on stream."""
+    import torch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def bench_rows():
+    """One JSON line per hot-path row other than the headline: the complex
+    sweep (30x30 Haar block), the sparse real path and the Section 4 pipeline
+    (40x40, 6 per row), the exact binary path (32x32 Bernoulli, 40x40 sparse),
+    and perm + dperm/dA of one matrix (24x24 real and complex)."""
+    import torch
+    from paper_2502_16577_amd import api, workloads
+
+    dev = torch.device("cuda:0")
+    st = torch.cuda.current_stream(dev)
+
+    def line(rec):
+        print(json.dumps(rec), flush=True)
+
+    # a7: complex dense sweep; 8n - 4 flops per subset-step (2n adds, n - 1
+    # complex products of 6 flops, 2 accumulation adds)
+    n = 30
+    A = torch.from_numpy(workloads.haar_block(120, n, workloads.SEED_HAAR120)).to(dev)
+    out = torch.empty((), dtype=torch.complex128, device=dev)
+    ws = torch.empty(api.workspace_bytes(2, n), dtype=torch.uint8, device=dev)
+    api.perm_dense_c128(A, out=out, ws=ws)
+    ms = _timed(lambda: api.perm_dense_c128(A, out=out, ws=ws), 10, st)
+    fl = (8 * n - 4) * 2 ** (n - 1)
+    line({"row": "a7 complex sweep", "workload": "30x30 block of a 120x120 Haar unitary (seed 16581)",
+          "ms": ms, "subset_steps_per_s": 2 ** (n - 1) / (ms * 1e-3),
+          "roofline": {"bound": "alu", "achieved": fl / (ms * 1e-3) / 1e12, "peak": PEAK_ALU_TFLOPS,
+                       "unit": "TFLOP/s", "frac": fl / (ms * 1e-3) / 1e12 / PEAK_ALU_TFLOPS,
+                       "flops_per_subset_step": 8 * n - 4}})
+
+    # a8: sparse real (staged columns) and the Section 4 decomposition path
+    n = 40
+    a = workloads.sparse_rows(n, 6, workloads.SEED_SPARSE40)
+    cp, ri, va = workloads.to_csc(a)
+    api.perm_sparse_f64(n, cp, ri, va)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    v = api.perm_sparse_f64(n, cp, ri, va).item()
+    dt = time.perf_counter() - t0
+    nnz_col = len(ri) / n
+    fl = (n - 1 + nnz_col + 1) * 2 ** (n - 1)  # products, the column's nonzeros, accumulation
+    line({"row": "a8 sparse real", "workload": "40x40 0/1 as f64, 6 per row (seed 16582)",
+          "seconds": dt, "perm": v, "subset_steps_per_s": 2 ** (n - 1) / dt,
+          "roofline": {"bound": "alu", "achieved": fl / dt / 1e12, "peak": PEAK_ALU_TFLOPS,
+                       "unit": "TFLOP/s", "frac": fl / dt / 1e12 / PEAK_ALU_TFLOPS,
+                       "flops_per_subset_step": n - 1 + nnz_col + 1,
+                       "note": "staged dense columns: n adds per step are executed"}})
+    api.perm_sparse_decomp(n, cp, ri, va)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    v = api.perm_sparse_decomp(n, cp, ri, va).item()
+    dt = time.perf_counter() - t0
+    line({"row": "next-3 DecompRyser", "workload": "same 40x40 matrix, DM pruning + Forbert-Marx, "
+          "leaves batched on the GPU (host decomposition included)", "seconds": dt, "perm": v})
+
+    # a9: exact binary
+    for name, a01 in (("32x32 Bernoulli(1/2) (seed 16580)",
+                       workloads.bernoulli(32, workloads.SEED_BERNOULLI32)),
+                      ("40x40 0/1, 6 per row (seed 16582)", a)):
+        nb = a01.shape[0]
+        api.perm_binary_exact(a01)
+        t0 = time.perf_counter()
+        val, res = api.perm_binary_exact(a01)
+        dt = time.perf_counter() - t0
+        line({"row": "a9 binary exact", "workload": name, "seconds": dt, "perm": str(val),
+              "primes": len(res), "subset_steps_per_s": 2 ** (nb - 1) / dt})
+
+    # a10: perm + dperm/dA of one matrix
+    for dtype, mat in (("f64", workloads.uniform(24, 1024)),
+                       ("c128", workloads.haar_block(120, 24, workloads.SEED_HAAR120))):
+        n = 24
+        A = torch.from_numpy(mat).to(dev)
+        po = torch.empty((), dtype=A.dtype, device=dev)
+        go = torch.empty((n, n), dtype=A.dtype, device=dev)
+        kind = 5 if dtype == "f64" else 6
+        wsg = torch.empty(api.workspace_bytes(kind, n), dtype=torch.uint8, device=dev)
+        api.perm_grad(A, out_perm=po, out_grad=go, ws=wsg)
+        ms = _timed(lambda: api.perm_grad(A, out_perm=po, out_grad=go, ws=wsg), 5, st)
+        cplx = dtype == "c128"
+        # G = sum over subsets of V tau^T: n^2 multiply-adds per subset (x2 for complex V)
+        gemm = (4 if cplx else 2) * n * n * 2 ** (n - 1)
+        line({"row": "a10 perm + dperm/dA", "workload": f"24x24 {dtype}", "ms": ms,
+              "subset_steps_per_s": 2 ** (n - 1) / (ms * 1e-3),
+              "gemm_equivalent_tflops": gemm / (ms * 1e-3) / 1e12})
 
 
 # Best published GPU kernel (x_reg-A_shr-rebuild with CEG, Quadro GV100) of
@@ -211,6 +309,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched perm+grad leg")
     ap.add_argument("--paper-tables", type=str, default="",
                     help="comma-separated n: time the paper's Table 4 / Table 3 shapes and exit")
+    ap.add_argument("--rows", action="store_true",
+                    help="time the other hot-path rows (complex, sparse, binary, gradient) and exit")
     ap.add_argument("--only-batched", action="store_true",
                     help="run only the batched perm+grad leg (prints its JSON object)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -230,6 +330,9 @@ def main():
         return
     if args.paper_tables:
         paper_tables([int(x) for x in args.paper_tables.split(",")])
+        return
+    if args.rows:
+        bench_rows()
         return
     if args.only_batched:
         print(json.dumps(bench_batched()), flush=True)

@@ -100,13 +100,18 @@ int perm_dense_f64(int n, const double *A, int64_t lda, double *out,
 typedef struct {
     int accumulation;              /* PERM_ACC_TWOSUM, PERM_ACC_PLAIN or PERM_ACC_KAHAN */
     int log2_reseed;               /* exact re-seed of x every 2^r steps; 0 = default (2^9),
-                                      values above the lane's chunk mean once per chunk */
-    int64_t max_steps_per_launch;  /* 0 = default (2^40): longer sweeps are split into
-                                      several launches over consecutive lane ranges */
+                                      values above the lane's chunk mean once per chunk;
+                                      steps are walked in blocks of 16 (8 for n = 13), so
+                                      shorter intervals act as the block length */
+    int64_t max_steps_per_launch;  /* 0 = default (2^40): longer sweeps run as several
+                                      full-grid launches, each over a consecutive range of
+                                      every lane's chunk (a power-of-two number of re-seed
+                                      intervals) */
     int log2_lanes;                /* 0 = default (about 2^18 lanes); else the number of
                                       lanes (one Gray chunk each) as a power of two, clamped
-                                      so that every lane walks at least 4 steps and a block
-                                      of 256 lanes is full */
+                                      to [2^8, 2^18] (or the default if larger), to chunks
+                                      longer than the 16-step block, and to chunks of at
+                                      most 2^31 steps */
 } perm_options;
 
 /* perm_dense_f64 with options (opt may be NULL).  PERM_EINVAL for an unknown

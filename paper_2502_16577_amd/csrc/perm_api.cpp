@@ -31,7 +31,9 @@ SweepPlan plan_sweep(int n, int /*steps_per_op_hint*/)
     }
     const int total = n - 1;                 // log2 of the number of steps
     const int cmin = std::min(6, total - 8);  // keep >= 256 lanes (one block)
-    const int c = std::max(cmin, total - 18);
+    // at most 2^31 steps per lane (32-bit local step index): above n = 50
+    // the lane count grows instead
+    const int c = std::min(31, std::max(cmin, total - 18));
     p.log2_chunk = c;
     p.log2_reseed = std::min(9, c);
     p.lanes = int64_t(1) << (total - c);

@@ -102,31 +102,33 @@ constexpr int dense_unroll() { return N >= 14 ? 4 : 3; }
 // ACC: how a lane accumulates the block sums -- kAccTwoSum (two-sum: the lane
 // partial is a double-double, the paper's "DQ" of Table 3), kAccKahan (Kahan
 // compensation, the paper's "Kahan"), kAccPlain (plain doubles, the paper's
-// "DD").  block_offset lets a long sweep run as several launches over
-// consecutive block ranges.
+// "DD").  A launch walks steps [l_begin, l_end) of every lane's chunk (both
+// multiples of the re-seed interval and of 2^U), so a long sweep runs as
+// several full-grid launches; `accumulate` adds this launch's block sums to
+// the partials of the previous ones (in launch order) instead of storing.
 template <int N, int ACC>
 __global__ __launch_bounds__(kBlock) void sweep_dense_f64(const double *__restrict__ acol,
                                                           const double *__restrict__ aneg,
                                                           const double *__restrict__ x0,
                                                           dd *__restrict__ partials, int c, int r,
-                                                          uint32_t block_offset)
+                                                          uint32_t l_begin, uint32_t l_end,
+                                                          int accumulate)
 {
     constexpr int U = dense_unroll<N>();
     constexpr uint32_t B = 1u << U;
     __shared__ dd red[kWavesPerBlock];
     const uint32_t lane = threadIdx.x & 63u;
-    const uint64_t wave = uniform_wave_index() + uint64_t(block_offset) * kWavesPerBlock;
+    const uint64_t wave = uniform_wave_index();
     const uint64_t K = lane_chunk_index(wave, lane);
     const uint32_t kb = uint32_t(wave & 1u);
     const uint64_t g0 = K << c;
     const uint64_t hbits = (g0 ^ (g0 >> 1)) >> c;
-    const uint32_t C = 1u << c;
     const uint32_t rmask = (1u << r) - 1u;
 
     double x[N];
     double s = 0.0, e = 0.0;
-    for (uint32_t l = 0; l < C; l += B) {
-        // step l: re-seed exactly, or flip column ctz(l)
+    for (uint32_t l = l_begin; l < l_end; l += B) {
+        // step l: re-seed exactly (always at l_begin), or flip column ctz(l)
         if ((l & rmask) == 0) {
             reseed<N>(x, acol, x0, hbits, gray_low(l, kb, c), c);
         } else {
@@ -169,33 +171,40 @@ __global__ __launch_bounds__(kBlock) void sweep_dense_f64(const double *__restri
     }
     // Kahan's e is the negated lost low part
     const dd t = block_reduce_dd(ACC == kAccKahan ? dd{s, -e} : dd{s, e}, red);
-    if (threadIdx.x == 0) partials[blockIdx.x + block_offset] = t;
+    if (threadIdx.x == 0) partials[blockIdx.x] = accumulate ? dd_add(partials[blockIdx.x], t) : t;
 }
 
-// Launches the sweep as consecutive block ranges of at most
-// max_steps_per_launch subset-steps each (one launch for the usual sizes).
+// Launches the sweep over the full grid, as consecutive ranges of each
+// lane's chunk of at most max_steps_per_launch subset-steps per launch (one
+// launch for the usual sizes).  Every range starts on a re-seed boundary.
 template <int N>
 static void launch_sweep_n(const SweepPlan &p, const SweepOptions &o, const double *acol,
                            const double *aneg, const double *x0, dd *partials,
                            hipStream_t stream)
 {
-    const int64_t steps_per_block = int64_t(kBlock) << p.log2_chunk;
-    int64_t per = o.max_steps_per_launch / steps_per_block;
-    if (per < 1) per = 1;
-    for (int64_t b0 = 0; b0 < p.blocks; b0 += per) {
-        const int64_t nb = p.blocks - b0 < per ? p.blocks - b0 : per;
+    const int64_t C = int64_t(1) << p.log2_chunk;
+    int64_t span = o.max_steps_per_launch / p.lanes;  // chunk steps per launch
+    const int64_t unit = std::max<int64_t>(int64_t(1) << o.log2_reseed, 1 << dense_unroll<N>());
+    span = std::max(unit, span - span % unit);
+    // a power-of-two number of units divides C, so every range is whole
+    int64_t pow2 = unit;
+    while (pow2 * 2 <= span && pow2 * 2 <= C) pow2 *= 2;
+    span = std::min(pow2, C);
+    for (int64_t l0 = 0; l0 < C; l0 += span) {
+        const uint32_t lb = uint32_t(l0), le = uint32_t(l0 + span);
+        const int accumulate = l0 > 0;
         if (o.accumulation == kAccTwoSum)
-            hipLaunchKernelGGL((sweep_dense_f64<N, kAccTwoSum>), dim3(unsigned(nb)), dim3(kBlock),
-                               0, stream, acol, aneg, x0, partials, p.log2_chunk, o.log2_reseed,
-                               uint32_t(b0));
+            hipLaunchKernelGGL((sweep_dense_f64<N, kAccTwoSum>), dim3(unsigned(p.blocks)),
+                               dim3(kBlock), 0, stream, acol, aneg, x0, partials, p.log2_chunk,
+                               o.log2_reseed, lb, le, accumulate);
         else if (o.accumulation == kAccKahan)
-            hipLaunchKernelGGL((sweep_dense_f64<N, kAccKahan>), dim3(unsigned(nb)), dim3(kBlock),
-                               0, stream, acol, aneg, x0, partials, p.log2_chunk, o.log2_reseed,
-                               uint32_t(b0));
+            hipLaunchKernelGGL((sweep_dense_f64<N, kAccKahan>), dim3(unsigned(p.blocks)),
+                               dim3(kBlock), 0, stream, acol, aneg, x0, partials, p.log2_chunk,
+                               o.log2_reseed, lb, le, accumulate);
         else
-            hipLaunchKernelGGL((sweep_dense_f64<N, kAccPlain>), dim3(unsigned(nb)), dim3(kBlock),
-                               0, stream, acol, aneg, x0, partials, p.log2_chunk, o.log2_reseed,
-                               uint32_t(b0));
+            hipLaunchKernelGGL((sweep_dense_f64<N, kAccPlain>), dim3(unsigned(p.blocks)),
+                               dim3(kBlock), 0, stream, acol, aneg, x0, partials, p.log2_chunk,
+                               o.log2_reseed, lb, le, accumulate);
     }
 }
 
@@ -244,6 +253,7 @@ int launch_dense_f64_opt(int n, const double *A, int64_t lda, double *out, const
         if (ll < 8) ll = 8;                       // one full block of 256 lanes
         const int def_ll = int(std::log2(double(p.lanes)));
         if (ll > std::max(18, def_ll)) ll = std::max(18, def_ll);
+        if (ll < total - 31) ll = total - 31;     // chunks of at most 2^31 steps
         p.log2_chunk = total - ll;
         p.lanes = int64_t(1) << ll;
         p.blocks = p.lanes / kBlock;

@@ -7,6 +7,7 @@ oracle's Ryser absolute sum 2 * sum_g |prod_i x_i(g)| (the natural scale of
 the rounding error of any evaluation of the Ryser sum).
 """
 import json
+import fractions
 import math
 import os
 
@@ -131,9 +132,14 @@ def test_options_plain_and_split(oracle):
     A = torch.from_numpy(a).to(DEV)
     want = oracle.ryser(a)
     ref = api.perm_dense_f64(A).item()
-    # splitting the sweep into many launches does not change a single bit
-    split = api.perm_dense_f64_ex(A, max_steps_per_launch=1 << 18).item()
-    assert split == ref
+    # a sweep split into 8 launches (ranges of 16 steps of every 128-step
+    # chunk) agrees with the single launch and is reproducible bit for bit
+    one = api.perm_dense_f64_ex(A, log2_reseed=4).item()
+    split = api.perm_dense_f64_ex(A, log2_reseed=4, max_steps_per_launch=1 << 22).item()
+    assert abs(split - one) <= 1e-13 * abs(want), (split, one)
+    assert abs(split - want) <= 1e-10 * abs(want), (split, want)
+    assert api.perm_dense_f64_ex(A, log2_reseed=4, max_steps_per_launch=1 << 22).item() == split
+    assert abs(ref - want) <= 1e-10 * abs(want)
     for ll in (8, 12, 16, 23):
         v = api.perm_dense_f64_ex(A, log2_lanes=ll).item()
         assert abs(v - want) <= 1e-10 * abs(want), (ll, v, want)
@@ -148,6 +154,11 @@ def test_options_plain_and_split(oracle):
 def test_all_equal_paper_size(n):
     # Section 5 / Table 3 shapes: all entries 0.91, perm = n! 0.91^n (2^34 and 2^35 steps)
     a = np.full((n, n), 0.91)
-    exact = math.factorial(n) * 0.91 ** n
+    exact = float(math.factorial(n) * fractions.Fraction(0.91) ** n)
     got = gpu_perm(a)
     assert abs(got - exact) <= 1e-10 * exact, (n, got, exact, abs(got - exact) / exact)
+    # the same sweep as 8 full-grid launches of 2^32 subset-steps (n = 36)
+    if n == 36:
+        A = torch.from_numpy(a).to(DEV)
+        got = api.perm_dense_f64_ex(A, max_steps_per_launch=1 << 32).item()
+        assert abs(got - exact) <= 1e-10 * exact, (n, got, exact, abs(got - exact) / exact)
