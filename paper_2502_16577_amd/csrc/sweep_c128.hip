@@ -5,6 +5,8 @@
 // Layout: acol[2*(j*N + i) + {0,1}] = (Re, Im) a_ij, aneg its negation,
 // x0[2*i + {0,1}] the start vector.  x lives in 2N VGPR pairs; the column of
 // each step is wave-uniform and read with scalar loads.
+#include <algorithm>
+
 #include "sweep_common.h"
 
 namespace perm {
@@ -103,13 +105,24 @@ __device__ __forceinline__ void creseed(double (&xr)[N], double (&xi)[N],
     }
 }
 
+// The lane walks its chunk in blocks of 2^U steps exactly as the real sweep
+// does: only the first step of a block flips a column chosen at run time;
+// steps l + m flip column ctz(m) with a sign fixed by m (by bit U of l for
+// m = 2^(U-1)).  The block's signed terms are summed in a chain before one
+// compensated update of each lane partial.  Requires c > U.
+template <int N>
+constexpr int cdense_unroll() { return N >= 14 ? 4 : 3; }
+
 template <int N>
 __global__ __launch_bounds__(kBlock) void sweep_dense_c128(const double *__restrict__ acol,
                                                            const double *__restrict__ aneg,
                                                            const double *__restrict__ x0,
                                                            dd *__restrict__ partials, int c,
-                                                           int r)
+                                                           int r, uint32_t l_begin,
+                                                           uint32_t l_end, int accumulate)
 {
+    constexpr int U = cdense_unroll<N>();
+    constexpr uint32_t B = 1u << U;
     __shared__ dd red[kWavesPerBlock];
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t wave = uniform_wave_index();
@@ -117,33 +130,49 @@ __global__ __launch_bounds__(kBlock) void sweep_dense_c128(const double *__restr
     const uint32_t kb = uint32_t(wave & 1u);
     const uint64_t g0 = K << c;
     const uint64_t hbits = (g0 ^ (g0 >> 1)) >> c;
-    const uint32_t C = 1u << c;
     const uint32_t rmask = (1u << r) - 1u;
 
     double xr[N], xi[N];
     double sr = 0.0, er = 0.0, si = 0.0, ei = 0.0;
-    for (uint32_t l = 0; l < C; l += 2) {
-        if ((l & rmask) == 0) {
+    for (uint32_t l = l_begin; l < l_end; l += B) {
+        if ((l & rmask) == 0) {  // always at l_begin, a re-seed boundary
             creseed<N>(xr, xi, acol, x0, hbits, gray_low(l, kb, c), c);
         } else {
             const int j = __builtin_ctz(l);
             const bool add = (gray_low(l, kb, c) >> j) & 1u;
             add_ccolumn<N>(xr, xi, (add ? acol : aneg) + 2 * j * N);
         }
-        double er_, ei_;
-        cproduct4<N>(xr, xi, er_, ei_);
-        const bool add0 = gray_low(l + 1, kb, c) & 1u;
-        add_ccolumn<N>(xr, xi, add0 ? acol : aneg);
-        double or_, oi_;
-        cproduct4<N>(xr, xi, or_, oi_);
-        acc_add(sr, er, er_ - or_);
-        acc_add(si, ei, ei_ - oi_);
+        double br, bi;
+        cproduct4<N>(xr, xi, br, bi);
+#pragma unroll
+        for (uint32_t m = 1; m < B; ++m) {
+            const int j = __builtin_ctz(m);
+            const bool neg = (j + 1 < U) ? ((m >> (j + 1)) & 1u) : ((l >> U) & 1u);
+            // a fresh opaque offset per step keeps the compiler from merging
+            // or hoisting these constant-address column loads (whole columns
+            // held in SGPRs would spill)
+            uint32_t zero = 0;
+            asm volatile("" : "+s"(zero));
+            add_ccolumn<N>(xr, xi, (neg ? aneg : acol) + 2 * j * N + zero);
+            double tr, ti;
+            cproduct4<N>(xr, xi, tr, ti);
+            if (m & 1u) {  // (-1)^g = (-1)^m since l is even
+                br -= tr;
+                bi -= ti;
+            } else {
+                br += tr;
+                bi += ti;
+            }
+        }
+        acc_add(sr, er, br);
+        acc_add(si, ei, bi);
     }
     const dd tr = block_reduce_dd(dd{sr, er}, red);
     const dd ti = block_reduce_dd(dd{si, ei}, red);
     if (threadIdx.x == 0) {
-        partials[2 * blockIdx.x] = tr;
-        partials[2 * blockIdx.x + 1] = ti;
+        dd *pp = partials + 2 * blockIdx.x;
+        pp[0] = accumulate ? dd_add(pp[0], tr) : tr;
+        pp[1] = accumulate ? dd_add(pp[1], ti) : ti;
     }
 }
 
@@ -151,8 +180,20 @@ template <int N>
 static void launch_csweep_n(const SweepPlan &p, const double *acol, const double *aneg,
                             const double *x0, dd *partials, hipStream_t stream)
 {
-    hipLaunchKernelGGL(sweep_dense_c128<N>, dim3(unsigned(p.blocks)), dim3(kBlock), 0, stream,
-                       acol, aneg, x0, partials, p.log2_chunk, p.log2_reseed);
+    // long sweeps: full-grid launches over consecutive ranges of every lane's
+    // chunk, each of at most 2^40 subset-steps and starting on a re-seed
+    // boundary; later launches add to the partials of earlier ones
+    const int64_t C = int64_t(1) << p.log2_chunk;
+    int64_t span = std::max<int64_t>((int64_t(1) << 40) / p.lanes,
+                                     std::max<int64_t>(int64_t(1) << p.log2_reseed,
+                                                       1 << cdense_unroll<N>()));
+    int64_t pow2 = 1;
+    while (pow2 * 2 <= span) pow2 *= 2;
+    span = std::min(pow2, C);
+    for (int64_t l0 = 0; l0 < C; l0 += span)
+        hipLaunchKernelGGL(sweep_dense_c128<N>, dim3(unsigned(p.blocks)), dim3(kBlock), 0, stream,
+                           acol, aneg, x0, partials, p.log2_chunk, p.log2_reseed, uint32_t(l0),
+                           uint32_t(l0 + span), int(l0 > 0));
 }
 
 using CSweepLauncher = void (*)(const SweepPlan &, const double *, const double *,
