@@ -70,7 +70,7 @@ def cpu_baseline(a, target_seconds=12.0):
                       f"({nch} chunks of {chunk} steps, long double), {dt:.2f} s wall"}
 
 
-def bench_batched(reps: int = 5):
+def bench_batched(reps: int = 5, use_graph: bool = True, baselines: bool = True):
     """Batched perm + dperm/dA of the 4096-matrix photon-counting batch (one
     hipGraph launch) against per-matrix launches: of perm_grad, and of the
     plain forward solver (perm_dense_c128 on the matrix and on each of its
@@ -89,15 +89,19 @@ def bench_batched(reps: int = 5):
     out, grad = plan.outputs(d)
     stream = torch.cuda.current_stream(dev)
     for _ in range(2):
-        plan.run(d, out=out, grad=grad, use_graph=True)
+        plan.run(d, out=out, grad=grad, use_graph=use_graph)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for _ in range(reps):
-        plan.run(d, out=out, grad=grad, use_graph=True)
+        plan.run(d, out=out, grad=grad, use_graph=use_graph)
     e1.record(stream)
     torch.cuda.synchronize()
     batch_ms = e0.elapsed_time(e1) / reps
+    if not baselines:
+        return {"matrices": 4096, "batch_ms": batch_ms, "value": 4096 / (batch_ms * 1e-3),
+                "unit": "matrices/s (perm+grad)", "graph": use_graph,
+                "autotuned": {"best_ms": tuned_ms, **plan.info()}}
 
     # per-matrix perm_grad launches over the whole batch
     dm = [torch.from_numpy(a).to(dev) for a in mats]
@@ -218,6 +222,22 @@ def bench_rows():
                        "unit": "TFLOP/s", "frac": fl / dt / 1e12 / PEAK_ALU_TFLOPS,
                        "flops_per_subset_step": n - 1 + nnz_col + 1,
                        "note": "staged dense columns: n adds per step are executed"}})
+    # the same matrix through the kernel generated for its pattern (the first
+    # call compiles it; the timed call reuses the cached module)
+    t0 = time.perf_counter()
+    api.perm_sparse_f64_gen(n, cp, ri, va)
+    torch.cuda.synchronize()
+    first = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    v = api.perm_sparse_f64_gen(n, cp, ri, va).item()
+    dt = time.perf_counter() - t0
+    # (no roofline: inside a 16-step block the generated product re-uses the
+    # product of the rows the block does not touch, so it executes far fewer
+    # operations than the n - 1 + nnz_j per step the method is priced at)
+    line({"row": "next-4 generated sparse kernel", "workload": "same 40x40 matrix, kernel "
+          "generated for its pattern (hiprtc)", "seconds": dt, "first_call_seconds": first,
+          "perm": v, "subset_steps_per_s": 2 ** (n - 1) / dt,
+          "method_flops_per_s": fl / dt})
     api.perm_sparse_decomp(n, cp, ri, va)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -315,6 +335,11 @@ def main():
                     help="time the other hot-path rows (complex, sparse, binary, gradient) and exit")
     ap.add_argument("--only-batched", action="store_true",
                     help="run only the batched perm+grad leg (prints its JSON object)")
+    ap.add_argument("--batched-eager", action="store_true",
+                    help="launch the batched leg's kernels directly instead of as a hipGraph "
+                         "(for counter collection, which does not follow graph launches)")
+    ap.add_argument("--batched-quick", action="store_true",
+                    help="batched leg without the per-matrix baselines (profiling runs)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (3 times) and exit; "
                          "used to scale FETCH_SIZE / WRITE_SIZE counters to bytes")
@@ -337,7 +362,8 @@ def main():
         bench_rows()
         return
     if args.only_batched:
-        print(json.dumps(bench_batched()), flush=True)
+        print(json.dumps(bench_batched(use_graph=not args.batched_eager,
+                                       baselines=not args.batched_quick)), flush=True)
         return
     if args.gpus != 1:
         print("bench.py: this build runs on exactly one GPU (no multi-GPU path); use --gpus 1",

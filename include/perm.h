@@ -54,6 +54,7 @@ typedef struct {
 #define PERM_EWORKSPACE   -3  /* ws NULL or ws_bytes below perm_workspace_bytes() */
 #define PERM_EHIP         -4  /* a HIP runtime call failed */
 #define PERM_EUNSUPPORTED -5  /* valid request this build does not implement */
+#define PERM_ECOMPILE     -6  /* run-time compilation of a generated kernel failed */
 
 /* Workspace kinds for perm_workspace_bytes(). */
 #define PERM_KIND_DENSE_F64   1
@@ -144,6 +145,21 @@ int perm_dense_c128(int n, const perm_c128 *A, int64_t lda, perm_c128 *out,
 int perm_sparse_f64(int n, const int32_t *col_ptr, const int32_t *row_idx,
                     const double *vals, int32_t nnz, double *out,
                     void *ws, size_t ws_bytes, void *stream);
+
+/* perm_sparse_f64 through a kernel generated for this sparsity pattern
+ * (Section 3.3's per-matrix code generation applied to Algorithm 2's sparse
+ * update): each column's update is compiled as a fixed list of additions to
+ * the rows holding its nonzeros, so a step costs the column's nonzeros
+ * instead of n additions.  Columns are reordered by ascending count first
+ * (the permanent does not change).  The first call for a pattern on a device
+ * compiles the kernel with hiprtc (about a second) and keeps it loaded until
+ * the process ends; later calls with the same pattern, whatever the values,
+ * reuse it.  Same arguments, workspace (PERM_KIND_SPARSE_F64) and
+ * synchronisation as perm_sparse_f64; n < 14 runs perm_sparse_f64 itself.
+ * PERM_ECOMPILE if the compilation fails. */
+int perm_sparse_f64_gen(int n, const int32_t *col_ptr, const int32_t *row_idx,
+                        const double *vals, int32_t nnz, double *out, void *ws, size_t ws_bytes,
+                        void *stream);
 
 /*
  * Exact permanent of a 0/1 matrix given by its nonzero pattern in CSC (the

@@ -18,6 +18,7 @@ PERM_ERANGE = -2
 PERM_EWORKSPACE = -3
 PERM_EHIP = -4
 PERM_EUNSUPPORTED = -5
+PERM_ECOMPILE = -6
 
 KIND_DENSE_F64 = 1
 KIND_DENSE_C128 = 2
@@ -42,6 +43,7 @@ SIGNATURES = [
     ("perm_dense_f64_ex", _int, [_int, _vp, _i64, _vp, _vp, _vp, _sz, _vp]),
     ("perm_dense_c128", _int, [_int, _vp, _i64, _vp, _vp, _sz, _vp]),
     ("perm_sparse_f64", _int, [_int, _vp, _vp, _vp, _i32, _vp, _vp, _sz, _vp]),
+    ("perm_sparse_f64_gen", _int, [_int, _vp, _vp, _vp, _i32, _vp, _vp, _sz, _vp]),
     ("perm_binary_exact", _int, [_int, _vp, _vp, _i32, _int, _vp, _vp, _vp, _vp, _sz, _vp]),
     ("perm_binary_prime", _u64, [_int]),
     ("perm_grad", _int, [_int, _int, _vp, _i64, _vp, _vp, _vp, _sz, _vp]),

@@ -122,6 +122,25 @@ def perm_sparse_f64(n: int, col_ptr, row_idx, vals, device="cuda:0", out=None, w
     return out
 
 
+def perm_sparse_f64_gen(n: int, col_ptr, row_idx, vals, device="cuda:0", out=None, ws=None):
+    """perm_sparse_f64 through a kernel generated and compiled (hiprtc) for
+    this sparsity pattern; the module is cached per device and pattern."""
+    col_ptr = np.ascontiguousarray(col_ptr, dtype=np.int32)
+    row_idx = np.ascontiguousarray(row_idx, dtype=np.int32)
+    vals = np.ascontiguousarray(vals, dtype=np.float64)
+    device = torch.device(device)
+    nnz = int(row_idx.size)
+    if out is None:
+        out = torch.empty((), dtype=torch.float64, device=device)
+    ws, need = _workspace(N.KIND_SPARSE_F64, n, nnz, device, ws)
+    st = N.lib().perm_sparse_f64_gen(n, col_ptr.ctypes.data if n else None,
+                                     row_idx.ctypes.data if nnz else None,
+                                     vals.ctypes.data if nnz else None, nnz, out.data_ptr(),
+                                     ws.data_ptr(), need, _stream(device))
+    N.check(st, "perm_sparse_f64_gen")
+    return out
+
+
 def perm(A: torch.Tensor) -> torch.Tensor:
     """Permanent of a dense float64 or complex128 CUDA matrix."""
     if A.dtype == torch.complex128:

@@ -178,6 +178,7 @@ const char *perm_strerror(int status)
     case PERM_EWORKSPACE: return "workspace missing or too small";
     case PERM_EHIP: return "HIP runtime error";
     case PERM_EUNSUPPORTED: return "unsupported request";
+    case PERM_ECOMPILE: return "run-time compilation of a generated kernel failed";
     default: return "unknown status";
     }
 }
@@ -281,6 +282,62 @@ int perm_sparse_f64(int n, const int32_t *col_ptr, const int32_t *row_idx, const
     // the host staging buffer must outlive the copy
     if (hipStreamSynchronize(st) != hipSuccess) return PERM_EHIP;
     return launch_dense_f64(n, reinterpret_cast<const double *>(base + off), n, out, base, st);
+}
+
+int perm_sparse_f64_gen(int n, const int32_t *col_ptr, const int32_t *row_idx,
+                        const double *vals, int32_t nnz, double *out, void *ws, size_t ws_bytes,
+                        void *stream)
+{
+    if (!valid_n(n) || !out) return PERM_EINVAL;
+    if (n > 0 && (!valid_csc(n, col_ptr, row_idx, nnz) || (nnz > 0 && !vals))) return PERM_EINVAL;
+    const int w = check_ws(ws, ws_bytes, perm_workspace_bytes(PERM_KIND_SPARSE_F64, n, nnz));
+    if (w != PERM_OK) return w;
+    if (n < kSparseGenMinN)  // a few thousand steps: the staged-column sweep
+        return perm_sparse_f64(n, col_ptr, row_idx, vals, nnz, out, ws, ws_bytes, stream);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char *base = static_cast<char *>(ws);
+    // Columns by ascending count (the permanent is invariant under column
+    // permutations): the low columns, flipped at 15 of every 16 steps, then
+    // cost the fewest updates, and the densest column is the never-flipped
+    // last one.
+    std::vector<int> order(n);
+    for (int j = 0; j < n; ++j) order[j] = j;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        return col_ptr[x + 1] - col_ptr[x] < col_ptr[y + 1] - col_ptr[y];
+    });
+    // Rows (also free to permute): those with a nonzero in the four lowest
+    // columns go last.  Steps inside a 16-step block change only these rows,
+    // and the generated product evaluates rows in a fixed order, so the
+    // compiler computes the product of the other rows once per block.
+    std::vector<char> hot(n, 0);
+    for (int jn = 0; jn < std::min(n, 4); ++jn)
+        for (int32_t q = col_ptr[order[jn]]; q < col_ptr[order[jn] + 1]; ++q) hot[row_idx[q]] = 1;
+    std::vector<int> new_row(n);
+    {
+        int k = 0;
+        for (int i = 0; i < n; ++i)
+            if (!hot[i]) new_row[i] = k++;
+        for (int i = 0; i < n; ++i)
+            if (hot[i]) new_row[i] = k++;
+    }
+    const size_t off = perm_workspace_bytes(PERM_KIND_DENSE_F64, n, 0);
+    std::vector<double> dense(size_t(n) * n, 0.0);
+    std::vector<std::vector<int>> rows(n);
+    for (int jn = 0; jn < n; ++jn) {
+        const int j = order[jn];
+        for (int32_t q = col_ptr[j]; q < col_ptr[j + 1]; ++q) {
+            const int i = new_row[row_idx[q]];
+            dense[size_t(i) * n + jn] = vals[q];
+            rows[jn].push_back(i);
+        }
+        std::sort(rows[jn].begin(), rows[jn].end());
+    }
+    if (hipMemcpyAsync(base + off, dense.data(), dense.size() * sizeof(double),
+                       hipMemcpyHostToDevice, st) != hipSuccess)
+        return PERM_EHIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return PERM_EHIP;  // staging buffer lifetime
+    return launch_sparse_gen(n, rows, reinterpret_cast<const double *>(base + off),
+                             out, base, st);
 }
 
 int perm_binary_exact(int n, const int32_t *col_ptr, const int32_t *row_idx, int32_t nnz,

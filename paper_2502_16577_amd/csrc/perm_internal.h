@@ -6,6 +6,9 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <string>
+#include <vector>
+
 #include "perm.h"
 
 namespace perm {
@@ -142,6 +145,15 @@ GradWs grad_ws_layout(int n, int components, int64_t waves);
 // Kernel launchers (defined in the .hip files).  All return PERM_OK or
 // PERM_EHIP and only enqueue work on `stream`.
 // ---------------------------------------------------------------------------
+// Matrix-specific sparse sweep (sparse_codegen.cpp): `rows[j]` lists the
+// nonzero rows of column j of the staged matrix `dense_dev` (row-major,
+// lda = n, on the device).  Compiles and caches one kernel per device and
+// pattern.
+constexpr int kSparseGenMinN = 14;
+int launch_sparse_gen(int n, const std::vector<std::vector<int>> &rows, const double *dense_dev,
+                      double *out, char *ws, hipStream_t stream);
+std::string sparse_gen_source(int n, const std::vector<std::vector<int>> &rows);
+
 int launch_dense_f64(int n, const double *A, int64_t lda, double *out, char *ws,
                      hipStream_t stream);
 int launch_dense_f64_opt(int n, const double *A, int64_t lda, double *out, const SweepOptions &o,

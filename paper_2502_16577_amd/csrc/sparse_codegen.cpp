@@ -1,0 +1,281 @@
+// Matrix-specific sparse sweep (the paper's per-matrix code generation,
+// Section 3.3, applied to the sparse update of Algorithm 2): the host writes
+// a HIP kernel in which the update of every column is a fixed list of
+// `x_r += a_rj` on named registers -- only the column's nonzeros, with
+// compile-time row indices -- compiles it for gfx950 with hiprtc, and keeps
+// the loaded module for the rest of the process, keyed by device and
+// sparsity pattern (the values are read from the staged column-major copy,
+// so matrices with the same pattern share one module).
+//
+// The generated kernel walks each lane's chunk in 16-step blocks exactly as
+// the dense sweep does (one column chosen at run time per block, the other
+// fifteen flips compile-time columns 0..3 with signs fixed by the step within
+// the block), re-seeds exactly every 2^r steps, accumulates block sums by
+// two-sum and writes one double-double partial per block.
+#include <hip/hip_runtime.h>
+#include <hip/hiprtc.h>
+
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "perm.h"
+#include "sweep_common.h"
+
+namespace perm {
+namespace {
+
+constexpr int kGenUnroll = 4;  // 16-step blocks
+
+// Device helpers of the generated source: double-double sums and the
+// wave / block reductions, in the same fixed order as the library's own.
+const char *kPrelude = R"(
+typedef unsigned int u32;
+typedef unsigned long long u64;
+struct dd { double hi, lo; };
+__device__ inline void two_sum(double a, double b, double &s, double &e)
+{ s = a + b; double bb = s - a; e = (a - (s - bb)) + (b - bb); }
+__device__ inline dd dd_add(dd a, dd b)
+{
+    double s, e; two_sum(a.hi, b.hi, s, e);
+    double t, f; two_sum(a.lo, b.lo, t, f);
+    e += t; double hi = s + e; double lo = e - (hi - s); lo += f;
+    double hi2 = hi + lo; return dd{hi2, lo - (hi2 - hi)};
+}
+__device__ inline dd block_reduce_dd(dd v, dd *lds)
+{
+    for (int off = 32; off >= 1; off >>= 1) {
+        dd o; o.hi = __shfl_xor(v.hi, off, 64); o.lo = __shfl_xor(v.lo, off, 64);
+        v = dd_add(v, o);
+    }
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+    __syncthreads();
+    dd t = dd{0.0, 0.0};
+    if (threadIdx.x == 0) { t = lds[0]; for (int w = 1; w < 4; ++w) t = dd_add(t, lds[w]); }
+    return t;
+}
+__device__ inline u32 gray_low(u32 l, u32 kb, int c)
+{ u32 g = l ^ (l >> 1) ^ (kb << (c - 1)); return g & ((1u << c) - 1u); }
+)";
+
+// Column j's update: op is "+=", "-=" or an FMA with the lane factor f.
+std::string column_code(int n, const std::vector<std::vector<int>> &rows, int j, char op)
+{
+    std::ostringstream o;
+    for (int r : rows[j]) {
+        const int off = j * n + r;
+        if (op == '+') o << "x" << r << " += a[" << off << "]; ";
+        else if (op == '-') o << "x" << r << " -= a[" << off << "]; ";
+        else o << "x" << r << " = __builtin_fma(f, a[" << off << "], x" << r << "); ";
+    }
+    return o.str();
+}
+
+std::string switch_code(int n, const std::vector<std::vector<int>> &rows, const char *var, char op)
+{
+    std::ostringstream o;
+    o << "switch (" << var << ") {\n";
+    for (int j = 0; j < n - 1; ++j) {
+        if (rows[j].empty()) continue;
+        o << "case " << j << ": " << column_code(n, rows, j, op) << "break;\n";
+    }
+    o << "default: break;\n}\n";
+    return o.str();
+}
+
+// Product of x0..x{n-1} in four interleaved chains (independent latency).
+std::string product_code(int n)
+{
+    std::ostringstream o;
+    o << "(";
+    for (int ch = 0; ch < 4; ++ch) {
+        if (ch == 2) o << ") * (";
+        else if (ch) o << " * ";
+        o << "(";
+        bool first = true;
+        for (int i = ch; i < n; i += 4) {
+            o << (first ? "" : " * ") << "x" << i;
+            first = false;
+        }
+        if (first) o << "1.0";
+        o << ")";
+    }
+    o << ")";
+    return o.str();
+}
+
+std::string kernel_source(int n, const std::vector<std::vector<int>> &rows)
+{
+    std::ostringstream o;
+    o << kPrelude;
+    o << "extern \"C\" __global__ __launch_bounds__(256) void perm_sparse_gen(\n"
+         "    const double *__restrict__ a, const double *__restrict__ xs, dd *__restrict__ partials,\n"
+         "    int c, int r, u32 l_begin, u32 l_end, int accumulate)\n{\n"
+         "    __shared__ dd red[4];\n"
+         "    const u32 lane = threadIdx.x & 63u;\n"
+         "    const u64 wave = u64(blockIdx.x) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);\n"
+         "    const u64 K = (wave & 1u) | (u64(lane) << 1) | ((wave >> 1) << 7);\n"
+         "    const u32 kb = u32(wave & 1u);\n"
+         "    const u64 g0 = K << c;\n"
+         "    const u64 hbits = (g0 ^ (g0 >> 1)) >> c;\n"
+         "    const u32 rmask = (1u << r) - 1u;\n";
+    o << "    double";
+    for (int i = 0; i < n; ++i) o << (i ? ", " : " ") << "x" << i;
+    o << ";\n    double s = 0.0, e = 0.0;\n";
+    o << "    for (u32 l = l_begin; l < l_end; l += 16u) {\n"
+         "        if ((l & rmask) == 0) {\n";
+    for (int i = 0; i < n; ++i) o << "            x" << i << " = xs[" << i << "];\n";
+    o << "            for (int j = c; j < " << n - 1 << "; ++j) {\n"
+         "                const double f = ((hbits >> (j - c)) & 1u) ? 1.0 : 0.0;\n"
+         "                "
+      << switch_code(n, rows, "j", 'f')
+      << "            }\n"
+         "            u32 low = gray_low(l, kb, c);\n"
+         "            while (low) {\n"
+         "                const int j = __builtin_ctz(low);\n"
+         "                low &= low - 1u;\n"
+         "                "
+      << switch_code(n, rows, "j", '+')
+      << "            }\n"
+         "        } else {\n"
+         "            const int j = __builtin_ctz(l);\n"
+         "            if ((gray_low(l, kb, c) >> j) & 1u) {\n"
+      << switch_code(n, rows, "j", '+') << "            } else {\n"
+      << switch_code(n, rows, "j", '-') << "            }\n"
+         "        }\n";
+    const std::string prod = product_code(n);
+    o << "        double t0 = " << prod << ";\n";
+    const int B = 1 << kGenUnroll;
+    for (int m = 1; m < B; ++m) {
+        const int j = __builtin_ctz(unsigned(m));
+        if (j + 1 < kGenUnroll) {
+            const bool neg = (m >> (j + 1)) & 1;
+            o << "        " << column_code(n, rows, j, neg ? '-' : '+') << "\n";
+        } else {  // sign from bit U of l
+            o << "        if ((l >> " << kGenUnroll << ") & 1u) { " << column_code(n, rows, j, '-')
+              << "} else { " << column_code(n, rows, j, '+') << "}\n";
+        }
+        o << "        double t" << m << " = " << prod << ";\n";
+    }
+    // signed block sum: (-1)^m, pairwise then a tree
+    o << "        const double v = ";
+    o << "(((t0 - t1) + (t2 - t3)) + ((t4 - t5) + (t6 - t7))) + "
+         "(((t8 - t9) + (t10 - t11)) + ((t12 - t13) + (t14 - t15)));\n";
+    o << "        double tt, er; two_sum(s, v, tt, er); s = tt; e += er;\n"
+         "    }\n"
+         "    const dd t = block_reduce_dd(dd{s, e}, red);\n"
+         "    if (threadIdx.x == 0) partials[blockIdx.x] = accumulate ? dd_add(partials[blockIdx.x], t) : t;\n"
+         "}\n";
+    return o.str();
+}
+
+struct GenModule {
+    hipModule_t mod = nullptr;
+    hipFunction_t fn = nullptr;
+};
+
+std::mutex g_mu;
+std::unordered_map<std::string, GenModule> g_cache;
+
+std::string cache_key(int dev, int n, const std::vector<std::vector<int>> &rows)
+{
+    std::string k;
+    auto put = [&](int v) { k.append(reinterpret_cast<const char *>(&v), sizeof(v)); };
+    put(dev);
+    put(n);
+    for (const auto &c : rows) {
+        put(int(c.size()));
+        for (int r : c) put(r);
+    }
+    return k;
+}
+
+int compile_module(int n, const std::vector<std::vector<int>> &rows, GenModule &out)
+{
+    const std::string src = kernel_source(n, rows);
+    hiprtcProgram prog;
+    if (hiprtcCreateProgram(&prog, src.c_str(), "perm_sparse_gen.hip", 0, nullptr, nullptr) !=
+        HIPRTC_SUCCESS)
+        return PERM_ECOMPILE;
+    const char *opts[] = {"--offload-arch=gfx950", "-O3", "-Xclang", "-target-feature",
+                          "-Xclang", "-packed-fp32-ops"};
+    const hiprtcResult cr = hiprtcCompileProgram(prog, 6, opts);
+    size_t sz = 0;
+    std::vector<char> code;
+    if (cr == HIPRTC_SUCCESS && hiprtcGetCodeSize(prog, &sz) == HIPRTC_SUCCESS && sz > 0) {
+        code.resize(sz);
+        if (hiprtcGetCode(prog, code.data()) != HIPRTC_SUCCESS) code.clear();
+    }
+    hiprtcDestroyProgram(&prog);
+    if (code.empty()) return PERM_ECOMPILE;
+    if (hipModuleLoadData(&out.mod, code.data()) != hipSuccess) return PERM_EHIP;
+    if (hipModuleGetFunction(&out.fn, out.mod, "perm_sparse_gen") != hipSuccess) return PERM_EHIP;
+    return PERM_OK;
+}
+
+}  // namespace
+
+std::string sparse_gen_source(int n, const std::vector<std::vector<int>> &rows)
+{
+    return kernel_source(n, rows);
+}
+
+int launch_sparse_gen(int n, const std::vector<std::vector<int>> &rows, const double *dense_dev,
+                      double *out, char *ws, hipStream_t stream)
+{
+    if (n < kSparseGenMinN || n > PERM_MAX_N) return PERM_EUNSUPPORTED;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return PERM_EHIP;
+    GenModule m;
+    {
+        std::lock_guard<std::mutex> lock(g_mu);
+        const std::string key = cache_key(dev, n, rows);
+        auto it = g_cache.find(key);
+        if (it == g_cache.end()) {
+            const int rc = compile_module(n, rows, m);
+            if (rc != PERM_OK) return rc;
+            g_cache.emplace(key, m);
+        } else {
+            m = it->second;
+        }
+    }
+    const SweepPlan p = plan_sweep(n, 0);
+    const DenseWs L = dense_ws_layout(n, 1, dense_ws_blocks(n));
+    double *acol = reinterpret_cast<double *>(ws + L.acol);
+    double *aneg = reinterpret_cast<double *>(ws + L.aneg);
+    double *x0 = reinterpret_cast<double *>(ws + L.x0);
+    dd *partials = reinterpret_cast<dd *>(ws + L.partials);
+    hipLaunchKernelGGL(prep_dense_f64, dim3(1), dim3(kBlock), 0, stream, n, dense_dev, int64_t(n),
+                       acol, aneg, x0);
+    // full-grid launches over ranges of every lane's chunk (at most 2^40
+    // subset-steps each), every range starting on a re-seed boundary
+    const int c = p.log2_chunk;
+    const int r = std::max(p.log2_reseed, kGenUnroll);
+    const int64_t C = int64_t(1) << c;
+    int64_t span = std::max<int64_t>((int64_t(1) << 40) / p.lanes, int64_t(1) << r);
+    int64_t pow2 = 1;
+    while (pow2 * 2 <= span) pow2 *= 2;
+    span = std::min(pow2, C);
+    for (int64_t l0 = 0; l0 < C; l0 += span) {
+        const double *a_arg = acol;
+        const double *x_arg = x0;
+        dd *p_arg = partials;
+        int c_arg = c, r_arg = r;
+        uint32_t lb = uint32_t(l0), le = uint32_t(l0 + span);
+        int acc = l0 > 0;
+        void *args[] = {&a_arg, &x_arg, &p_arg, &c_arg, &r_arg, &lb, &le, &acc};
+        if (hipModuleLaunchKernel(m.fn, unsigned(p.blocks), 1, 1, kBlock, 1, 1, 0, stream, args,
+                                  nullptr) != hipSuccess)
+            return PERM_EHIP;
+    }
+    const double scale = (n & 1) ? 2.0 : -2.0;  // 2 (-1)^(n-1)
+    hipLaunchKernelGGL(finalize_partials, dim3(1), dim3(kBlock), 0, stream, partials, p.blocks, 1,
+                       scale, out);
+    return hipGetLastError() == hipSuccess ? PERM_OK : PERM_EHIP;
+}
+
+}  // namespace perm

@@ -34,6 +34,7 @@ def test_strerror_and_version():
     lib = N.lib()
     assert lib.perm_strerror(0) == b"success"
     assert lib.perm_strerror(N.PERM_EINVAL) == b"invalid argument"
+    assert b"compilation" in lib.perm_strerror(N.PERM_ECOMPILE)
     assert lib.perm_version() >= 100
 
 
@@ -116,10 +117,11 @@ def test_binary_primes_are_primes_below_2_61():
     assert lib.perm_binary_prime(5) == 0
 
 
-def test_sparse_argument_errors():
+@pytest.mark.parametrize("name", ["perm_sparse_f64", "perm_sparse_f64_gen"])
+def test_sparse_argument_errors(name):
     import numpy as np
     lib = N.lib()
-    f = lib.perm_sparse_f64
+    f = getattr(lib, name)
     cp = np.array([0, 1, 2], np.int32)
     ri = np.array([0, 1], np.int32)
     v = np.array([1.0, 2.0])
