@@ -276,7 +276,7 @@ class BatchedPlan:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
+        if h is not None and h.value and N is not None:  # N is None at interpreter exit
             N.lib().perm_plan_destroy(h)
             self._h = None
 

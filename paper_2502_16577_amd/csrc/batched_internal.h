@@ -7,20 +7,25 @@
 namespace perm {
 
 constexpr int kBatchMaxK = 32;
+constexpr int kBatchThreads = 128;  // one grad_item (two waves) per block
+
+// Staged rows per column of an order-k matrix (grad_item pads to an even
+// count so the two waves get equal row slices).
+__host__ __device__ inline int batch_rows(int k) { return k + (k & 1); }
 
 // One matrix of the batch.
 struct BatchMatDev {
     int32_t k;         // order
     int32_t c;         // log2 of the Gray steps per lane
     int32_t r;         // log2 of the exact re-seed interval (r <= c - 1)
-    int32_t waves;     // items (one wave each) covering its 2^(k-1) steps
+    int32_t waves;     // items (64 subsets each) covering its 2^(k-1) steps
     int64_t data_off;  // element offset of the matrix in the packed data (and grad)
     int64_t stage;     // double offset of its staged column copies
     int64_t item0;     // index of its first item among all items (matrix-major)
     int64_t gbase;     // dd offset of its first item's gradient partial
 };
 
-// One work item: wave w of matrix m.
+// One work item: subsets 64 w .. 64 w + 63 of matrix m.
 struct BatchItemDev {
     int32_t m;
     int32_t w;

@@ -1,5 +1,9 @@
-// One wave's share of the permanent-and-gradient sweep: 64 lanes, lane K =
-// 64 w + lane walks the Gray steps g in [K 2^c, (K+1) 2^c) of one matrix.
+// One work item of the permanent-and-gradient sweep: 64 subsets (lane K =
+// 64 w + lane walks the Gray steps g in [K 2^c, (K+1) 2^c) of one matrix),
+// processed by a block of NS = 2 waves that split the matrix's rows: wave h
+// holds rows [h R, (h+1) R) of every subset's x, window sum and
+// leave-one-out products, so each wave keeps half the state in registers.
+// Once per step the waves swap the products of their halves through LDS.
 // Shared by the single-matrix kernel (sweep_grad.hip) and the batched
 // persistent kernels (sweep_batched.hip).
 //
@@ -15,16 +19,20 @@
 //   * columns j >= f: the rank-1 updates of a window add up to W tau^T with
 //     W = sum of V over the window (one vector per lane); at the end of each
 //     window the 64 lanes' W are contracted with their tau as one FP64 MFMA
-//     product, G (n x n) += W (n x 64) T (64 x n), K running over the lanes.
+//     product, G (rows x n) += W (rows x 64) T (64 x n), K running over lanes.
 //   * columns j < f: tau_j depends only on the step (the same for every lane
 //     of the wave), so per step G[:, j] += tau_j U with U = sum over lanes of
-//     V; each lane sums 16 lanes' V from LDS and one MFMA per tile with the
-//     B operand tau_j repeated down K adds the four partial sums and forms the
-//     outer product with tau in one instruction.
+//     V; each lane sums 16 lanes' V from LDS and one MFMA with the B operand
+//     tau_j repeated down K adds the four partial sums and forms the outer
+//     product with tau in one instruction.
 // MFMA operand layout (gfx950): A[i][k] at lane i + 16k, B[k][j] at lane
 // j + 16k, D[i][j] at lane j + 16 (i mod 4), register i / 4.
 // Accumulators fold into the item's double-double partial G in global memory
 // at the end of every window.
+//
+// Staged layout: acol / aneg hold column j at [W (j NP + i)] with NP = NS R
+// rows (rows >= n are zero) and x0 has NP entries (1 for rows >= n), so a
+// padding row keeps x = 1 and changes no product.
 #pragma once
 
 #include "sweep_common.h"
@@ -55,18 +63,28 @@ __device__ __forceinline__ void wave_sync_lds()
 
 template <int N, bool CPLX>
 struct GradItemShape {
-    static constexpr int MT = (N + 15) / 16;   // 16-row tiles of G
-    static constexpr int STRIDE = 16 * MT + 1;  // doubles per lane row in LDS
-    static constexpr int W = CPLX ? 2 : 1;      // components
-    static constexpr int LDS_DOUBLES = W * kWave * STRIDE;
+    static constexpr int NS = 2;                  // waves (row slices) per item
+    static constexpr int R = (N + NS - 1) / NS;   // rows per slice (<= 16 for N <= 32)
+    static constexpr int NP = NS * R;             // staged rows per column
+    static constexpr int MT = (N + 15) / 16;      // 16-column tiles of G
+    static constexpr int STRIDE = R + 1;          // doubles per lane row in LDS
+    static constexpr int W = CPLX ? 2 : 1;        // components
+    static constexpr int VBUF = W * kWave * STRIDE;   // per-wave transposition buffer
+    static constexpr int XBUF = 2 * NS * kWave * W;   // product exchange, two step parities
+    static constexpr int LDS_DOUBLES = NS * VBUF + XBUF;
+    static constexpr int THREADS = NS * kWave;
+    static_assert(R <= 16, "a slice must fit one 16-row MFMA tile");
 };
 
-// Inputs: staged acol / aneg ([j*N + i], W doubles per entry) and x0; the
-// wave index w; log2 chunk c >= 1; log2 re-seed interval r <= c - 1;
-// lanes_active (lanes with K >= lanes_active idle with x = 0).
-// Outputs: perm_out[0..1] (double-double re, im of the wave's share of
-// sum_g (-1)^g prod x), and, if want_grad, g_out[(i*N + j)*W + comp]
-// (double-double share of sum_g (-1)^g L_i tau_j, zeroed here).
+// Called by all NS waves of a block (each must make the call: it
+// synchronises the block once per step).
+// Inputs: staged acol / aneg / x0 (layout above); the item's index w (its
+// subsets are 64 w .. 64 w + 63); log2 chunk c >= 1; log2 re-seed interval
+// r <= c - 1; lanes_active (subsets K >= lanes_active idle with x = 0).
+// Outputs: perm_out[0..1] (double-double re, im of the item's share of
+// sum_g (-1)^g prod x, written by wave 0), and, if want_grad,
+// g_out[(i*N + j)*W + comp] for i < N (double-double share of
+// sum_g (-1)^g L_i tau_j; each wave zeroes and fills its own rows).
 template <int N, bool CPLX>
 __device__ __forceinline__ void grad_item(const double *__restrict__ acol,
                                           const double *__restrict__ aneg,
@@ -76,10 +94,17 @@ __device__ __forceinline__ void grad_item(const double *__restrict__ acol,
                                           double *__restrict__ lds)
 {
     using S = GradItemShape<N, CPLX>;
+    constexpr int NS = S::NS;
+    constexpr int R = S::R;
+    constexpr int NP = S::NP;
     constexpr int MT = S::MT;
     constexpr int W = S::W;
     constexpr int STRIDE = S::STRIDE;
     const uint32_t lane = threadIdx.x & 63u;
+    const int h = int(__builtin_amdgcn_readfirstlane(threadIdx.x >> 6));  // row slice
+    const int row0 = h * R;
+    double *vbuf = lds + h * S::VBUF;
+    double *xbuf = lds + NS * S::VBUF;
     const uint32_t C = 1u << c;
     const uint32_t rmask = (1u << r) - 1u;
     const int f = c - 1 < 5 ? c - 1 : 5;  // window = 2^f steps
@@ -89,46 +114,47 @@ __device__ __forceinline__ void grad_item(const double *__restrict__ acol,
     const int jj = int(lane & 15u);      // B column / A row within a tile
     const int kq = int(lane >> 4);       // K index within an MFMA (0..3)
 
-    double xr[N], xi[N];
-    double wr[N], wi[N];                 // window sums of V
-    v4d acc_lo[W][MT];                   // low columns (j < f), N-tile 0 only
+    double xr[R], xi[R];
+    double wr[R], wi[R];                 // window sums of V (this slice's rows)
+    v4d acc_lo[W];                       // low columns (j < f)
 #pragma unroll
-    for (int q = 0; q < W; ++q)
+    for (int q = 0; q < W; ++q) acc_lo[q] = v4d{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int a = 0; a < MT; ++a) acc_lo[q][a] = v4d{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-        wr[i] = 0.0;
-        wi[i] = 0.0;
+    for (int t = 0; t < R; ++t) {
+        wr[t] = 0.0;
+        wi[t] = 0.0;
     }
-    if (want_grad)
-        for (int e = int(lane); e < W * N * N; e += kWave) g_out[e] = dd{0.0, 0.0};
+    if (want_grad) {
+        const int rows = N - row0 < R ? N - row0 : R;
+        for (int e = int(lane); e < rows * N * W; e += kWave) g_out[row0 * N * W + e] = dd{0.0, 0.0};
+    }
     double sr = 0.0, er = 0.0, si = 0.0, ei = 0.0;
 
     auto reseed = [&](uint32_t l) {
         const uint64_t g = (Kl << c) | l;
         const uint64_t gray = g ^ (g >> 1);
+        const double *xs = x0 + W * row0;
 #pragma unroll
-        for (int i = 0; i < N; ++i) {
-            xr[i] = act * x0[W * i];
-            xi[i] = CPLX ? act * x0[W * i + 1] : 0.0;
+        for (int t = 0; t < R; ++t) {
+            xr[t] = act * xs[W * t];
+            xi[t] = CPLX ? act * xs[W * t + 1] : 0.0;
         }
         for (int j = 0; j < N - 1; ++j) {
             const double fj = ((gray >> j) & 1u) ? act : 0.0;
-            const double *a = acol + W * j * N;
+            const double *a = acol + W * (j * NP + row0);
 #pragma unroll
-            for (int i = 0; i < N; ++i) {
-                xr[i] = __builtin_fma(fj, a[W * i], xr[i]);
-                if (CPLX) xi[i] = __builtin_fma(fj, a[W * i + 1], xi[i]);
+            for (int t = 0; t < R; ++t) {
+                xr[t] = __builtin_fma(fj, a[W * t], xr[t]);
+                if (CPLX) xi[t] = __builtin_fma(fj, a[W * t + 1], xi[t]);
             }
         }
     };
     auto flip = [&](int j, bool add) {
-        const double *a = (add ? acol : aneg) + W * j * N;
+        const double *a = (add ? acol : aneg) + W * (j * NP + row0);
 #pragma unroll
-        for (int i = 0; i < N; ++i) {
-            xr[i] = __builtin_fma(act, a[W * i], xr[i]);
-            if (CPLX) xi[i] = __builtin_fma(act, a[W * i + 1], xi[i]);
+        for (int t = 0; t < R; ++t) {
+            xr[t] = __builtin_fma(act, a[W * t], xr[t]);
+            if (CPLX) xi[t] = __builtin_fma(act, a[W * t + 1], xi[t]);
         }
     };
 
@@ -142,14 +168,14 @@ __device__ __forceinline__ void grad_item(const double *__restrict__ acol,
 
     auto step = [&](uint32_t l) {
         const double sg = (l & 1u) ? -1.0 : 1.0;  // (-1)^g = (-1)^l
-        // Leave-one-out products in four interleaved row blocks (four
-        // independent dependency chains): pass 1 forms prefix products inside
-        // each block and the block products P_b; then E_b = prod of the other
-        // blocks' P; pass 2 runs the suffix inside each block starting from
-        // sg * E_b, so L_i = prefix_i * sg * E_b * suffix_i.
-        constexpr int NB = N >= 8 ? 4 : 1;
-        constexpr int BS = (N + NB - 1) / NB;
-        double pr[N], pim[N];
+        // Leave-one-out products of the slice in NB interleaved row blocks
+        // (independent dependency chains): pass 1 forms prefix products
+        // inside each block and the block products P_b; E_b = product of the
+        // other blocks and of the other slice, times the sign; pass 2 runs the
+        // suffix inside each block from E_b, so L_i = prefix_i E_b suffix_i.
+        constexpr int NB = R >= 8 ? 4 : (R >= 4 ? 2 : 1);
+        constexpr int BS = (R + NB - 1) / NB;
+        double pr[R], pim[R];
         double br[NB], bi[NB];
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
@@ -161,39 +187,51 @@ __device__ __forceinline__ void grad_item(const double *__restrict__ acol,
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
                 const int i = b * BS + t;
-                if (i < N) {
+                if (i < R) {
                     pr[i] = br[b];
                     pim[i] = bi[b];
                     gmul<CPLX>(br[b], bi[b], xr[i], xi[i]);
                 }
             }
-        double er_[NB], ei_[NB];  // E_b: product of the other blocks
-        {
-            double fr = 1.0, fi = 0.0;  // prefix over blocks
+        double er_[NB], ei_[NB];    // E_b
+        double fr = 1.0, fi = 0.0;  // prefix over blocks; ends as the slice product
 #pragma unroll
-            for (int b = 0; b < NB; ++b) {
-                er_[b] = fr;
-                ei_[b] = fi;
-                gmul<CPLX>(fr, fi, br[b], bi[b]);
-            }
-            acc_add(sr, er, sg * fr);  // fr = the whole product
-            if (CPLX) acc_add(si, ei, sg * fi);
-            double gr = sg, gi = 0.0;  // suffix over blocks, with the sign
+        for (int b = 0; b < NB; ++b) {
+            er_[b] = fr;
+            ei_[b] = fi;
+            gmul<CPLX>(fr, fi, br[b], bi[b]);
+        }
+        // the other slice's product, through LDS (the buffer alternates with
+        // the step parity, so one barrier per step suffices)
+        double *xb = xbuf + int(l & 1u) * NS * kWave * W;
+        xb[(h * kWave + lane) * W] = fr;
+        if (CPLX) xb[(h * kWave + lane) * W + 1] = fi;
+        __syncthreads();
+        const double orr = xb[((1 - h) * kWave + lane) * W];
+        const double oii = CPLX ? xb[((1 - h) * kWave + lane) * W + 1] : 0.0;
+        if (h == 0) {  // the whole product, counted once per item
+            double pr0 = fr, pi0 = fi;
+            gmul<CPLX>(pr0, pi0, orr, oii);
+            acc_add(sr, er, sg * pr0);
+            if (CPLX) acc_add(si, ei, sg * pi0);
+        }
+        if (!want_grad) return;
+        {
+            double gr = sg * orr, gi = sg * oii;  // suffix over blocks, with the sign
 #pragma unroll
             for (int b = NB - 1; b >= 0; --b) {
                 gmul<CPLX>(er_[b], ei_[b], gr, gi);
                 gmul<CPLX>(gr, gi, br[b], bi[b]);
             }
         }
-        if (!want_grad) return;
-        double *vr = lds + lane * STRIDE;
-        double *vi = lds + (W - 1) * kWave * STRIDE + lane * STRIDE;
+        double *vr = vbuf + lane * STRIDE;
+        double *vi = vbuf + (W - 1) * kWave * STRIDE + lane * STRIDE;
 #pragma unroll
         for (int t = BS - 1; t >= 0; --t)
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
                 const int i = b * BS + t;
-                if (i < N) {
+                if (i < R) {
                     double lr = pr[i], li = pim[i];
                     gmul<CPLX>(lr, li, er_[b], ei_[b]);
                     wr[i] += lr;
@@ -207,30 +245,26 @@ __device__ __forceinline__ void grad_item(const double *__restrict__ acol,
             }
         if (f == 0) return;
         wave_sync_lds();
-        // low columns j < f: lane sums 16 lanes' V (rows kq*16 .. +15) of
-        // matrix row i = 16a + jj; the MFMA adds the 4 partial sums and
-        // multiplies by tau_j(l) (the same for every lane).
+        // low columns j < f: lane sums 16 lanes' V (lanes kq*16 .. +15) of
+        // slice row jj; the MFMA adds the 4 partial sums and multiplies by
+        // tau_j(l) (the same for every lane).
         const double bl = (jj < f) ? tau(0, l, jj) : 0.0;
 #pragma unroll
-        for (int a = 0; a < MT; ++a) {
-            const int i = 16 * a + jj;
+        for (int q = 0; q < W; ++q) {
+            double s = 0.0;
+            if (jj < R) {
+                const double *col = vbuf + q * kWave * STRIDE + jj + 16 * kq * STRIDE;
+                double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
 #pragma unroll
-            for (int q = 0; q < W; ++q) {
-                double s = 0.0;
-                if (i < N) {
-                    const double *col = lds + q * kWave * STRIDE + i + 16 * kq * STRIDE;
-                    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-#pragma unroll
-                    for (int rr = 0; rr < 16; rr += 4) {
-                        s0 += col[rr * STRIDE];
-                        s1 += col[(rr + 1) * STRIDE];
-                        s2 += col[(rr + 2) * STRIDE];
-                        s3 += col[(rr + 3) * STRIDE];
-                    }
-                    s = (s0 + s1) + (s2 + s3);
+                for (int rr = 0; rr < 16; rr += 4) {
+                    s0 += col[rr * STRIDE];
+                    s1 += col[(rr + 1) * STRIDE];
+                    s2 += col[(rr + 2) * STRIDE];
+                    s3 += col[(rr + 3) * STRIDE];
                 }
-                acc_lo[q][a] = __builtin_amdgcn_mfma_f64_16x16x4f64(s, bl, acc_lo[q][a], 0, 0, 0);
+                s = (s0 + s1) + (s2 + s3);
             }
+            acc_lo[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(s, bl, acc_lo[q], 0, 0, 0);
         }
         wave_sync_lds();
     };
@@ -238,21 +272,19 @@ __device__ __forceinline__ void grad_item(const double *__restrict__ acol,
     // End of a window: contract the lanes' window sums with their tau for
     // the columns j >= f, then fold everything into the double-double G.
     auto close_window = [&](uint32_t l0) {
-        v4d acc_hi[W][MT][MT];  // the window's contraction
+        v4d acc_hi[W][MT];  // the window's contraction (slice rows x all columns)
 #pragma unroll
         for (int q = 0; q < W; ++q)
 #pragma unroll
-            for (int a = 0; a < MT; ++a)
+            for (int b = 0; b < MT; ++b) acc_hi[q][b] = v4d{0.0, 0.0, 0.0, 0.0};
+        double *vr = vbuf + lane * STRIDE;
+        double *vi = vbuf + (W - 1) * kWave * STRIDE + lane * STRIDE;
 #pragma unroll
-                for (int b = 0; b < MT; ++b) acc_hi[q][a][b] = v4d{0.0, 0.0, 0.0, 0.0};
-        double *vr = lds + lane * STRIDE;
-        double *vi = lds + (W - 1) * kWave * STRIDE + lane * STRIDE;
-#pragma unroll
-        for (int i = 0; i < N; ++i) {
-            vr[i] = wr[i];
-            if (CPLX) vi[i] = wi[i];
-            wr[i] = 0.0;
-            wi[i] = 0.0;
+        for (int t = 0; t < R; ++t) {
+            vr[t] = wr[t];
+            if (CPLX) vi[t] = wi[t];
+            wr[t] = 0.0;
+            wi[t] = 0.0;
         }
         wave_sync_lds();
 #pragma unroll 2
@@ -262,45 +294,42 @@ __device__ __forceinline__ void grad_item(const double *__restrict__ acol,
 #pragma unroll
             for (int b = 0; b < MT; ++b) {
                 const int j = 16 * b + jj;
-                bop[b] = (j >= f) ? tau(lk, l0, j) * (lk < lanes_active ? 1.0 : 0.0) : 0.0;
+                bop[b] = (j >= f) ? tau(lk, l0, j) * (w * kWave + lk < lanes_active ? 1.0 : 0.0)
+                                  : 0.0;
             }
 #pragma unroll
-            for (int a = 0; a < MT; ++a) {
-                const int i = 16 * a + jj;
+            for (int q = 0; q < W; ++q) {
+                const double av = (jj < R) ? vbuf[q * kWave * STRIDE + lk * STRIDE + jj] : 0.0;
 #pragma unroll
-                for (int q = 0; q < W; ++q) {
-                    const double av = (i < N) ? lds[q * kWave * STRIDE + lk * STRIDE + i] : 0.0;
-#pragma unroll
-                    for (int b = 0; b < MT; ++b)
-                        acc_hi[q][a][b] =
-                            __builtin_amdgcn_mfma_f64_16x16x4f64(av, bop[b], acc_hi[q][a][b], 0, 0, 0);
-                }
+                for (int b = 0; b < MT; ++b)
+                    acc_hi[q][b] =
+                        __builtin_amdgcn_mfma_f64_16x16x4f64(av, bop[b], acc_hi[q][b], 0, 0, 0);
             }
         }
         wave_sync_lds();
-        // fold into the item's partial G
+        // fold into the item's partial G (this slice's rows)
 #pragma unroll
         for (int q = 0; q < W; ++q)
 #pragma unroll
-            for (int a = 0; a < MT; ++a)
+            for (int b = 0; b < MT; ++b) {
 #pragma unroll
-                for (int b = 0; b < MT; ++b) {
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const int i = 16 * a + kq + 4 * e;
-                        const int j = 16 * b + jj;
-                        double v = acc_hi[q][a][b][e];
-                        if (b == 0) v += acc_lo[q][a][e];
-                        if (i < N && j < N) {
-                            dd *p = g_out + (i * N + j) * W + q;
-                            const dd o = *p;
-                            double s, t;
-                            two_sum(o.hi, v, s, t);
-                            *p = dd{s, o.lo + t};
-                        }
+                for (int e = 0; e < 4; ++e) {
+                    const int t = kq + 4 * e;  // slice row
+                    const int i = row0 + t;
+                    const int j = 16 * b + jj;
+                    double v = acc_hi[q][b][e];
+                    if (b == 0) v += acc_lo[q][e];
+                    if (t < R && i < N && j < N) {
+                        dd *p = g_out + (i * N + j) * W + q;
+                        const dd o = *p;
+                        double s, u;
+                        two_sum(o.hi, v, s, u);
+                        *p = dd{s, o.lo + u};
                     }
-                    if (b == 0) acc_lo[q][a] = v4d{0.0, 0.0, 0.0, 0.0};
                 }
+            }
+#pragma unroll
+        for (int q = 0; q < W; ++q) acc_lo[q] = v4d{0.0, 0.0, 0.0, 0.0};
     };
 
     for (uint32_t l = 0; l < C; l += 2) {
@@ -321,11 +350,13 @@ __device__ __forceinline__ void grad_item(const double *__restrict__ acol,
         step(l + 1);
         if (want_grad && ((l + 2) & fmask) == 0) close_window((l + 1) & ~fmask);
     }
-    const dd pr = wave_reduce_dd(dd{sr, er});
-    const dd pi = wave_reduce_dd(dd{si, ei});
-    if (lane == 0) {
-        perm_out[0] = pr;
-        perm_out[1] = pi;
+    if (h == 0) {
+        const dd pr = wave_reduce_dd(dd{sr, er});
+        const dd pi = wave_reduce_dd(dd{si, ei});
+        if (lane == 0) {
+            perm_out[0] = pr;
+            perm_out[1] = pi;
+        }
     }
 }
 

@@ -140,6 +140,8 @@ struct GradWs {
 };
 
 GradWs grad_ws_layout(int n, int components, int64_t waves);
+// Staged rows per column for grad_item (padded to the two row slices).
+inline int grad_rows(int n) { return n + (n & 1); }
 
 // ---------------------------------------------------------------------------
 // Kernel launchers (defined in the .hip files).  All return PERM_OK or

@@ -1,11 +1,12 @@
 // Batched permanents (and gradients) of many small complex matrices of
 // uneven order in one persistent launch.
 //
-// The batch is cut into work items: item (m, w) is wave w of matrix m, and
-// covers 64 lanes x 2^c Gray steps of that matrix (lane K = 64 w + lane
-// walks g in [K 2^c, (K+1) 2^c)).  A persistent grid of one-wave blocks pulls
-// items from an atomic counter, largest matrices first, and dispatches on
-// the (wave-uniform) order k to a sweep compiled for that k.  Each item writes
+// The batch is cut into work items: item (m, w) covers subsets 64 w ..
+// 64 w + 63 of matrix m, each walking 2^c Gray steps (subset K walks g in
+// [K 2^c, (K+1) 2^c)).  A persistent grid of two-wave blocks (one item at a
+// time, the waves splitting the rows) pulls items from an atomic counter,
+// largest matrices first, and dispatches on the (block-uniform) order k to a
+// sweep compiled for that k.  Each item writes
 // its own double-double partials (permanent, and G if requested); a
 // segmented finalize sums the items of every matrix in a fixed order, so the
 // result does not depend on which wave ran which item.
@@ -19,25 +20,32 @@
 
 namespace perm {
 
-// Stages every matrix: acol[2(j k + i) + {re,im}], aneg = -acol, x0[2 i + {re,im}]
-// at stage + mats[m].stage (doubles).  One block per matrix.
+// Stages every matrix in grad_item's layout: acol[2(j kp + i) + {re,im}]
+// with kp = batch_rows(k) rows per column (rows >= k zero), aneg = -acol,
+// x0[2 i + {re,im}] for i < kp (1 for rows >= k), at stage + mats[m].stage
+// (doubles).  One block per matrix.
 __global__ __launch_bounds__(kBlock) void batched_prep(const BatchMatDev *__restrict__ mats,
                                                        const perm_c128 *__restrict__ data,
                                                        double *__restrict__ stage)
 {
     const BatchMatDev M = mats[blockIdx.x];
     const int k = M.k;
+    const int kp = batch_rows(k);
     const perm_c128 *A = data + M.data_off;
     double *acol = stage + M.stage;
-    double *aneg = acol + 2 * k * k;
-    double *x0 = aneg + 2 * k * k;
-    for (int idx = threadIdx.x; idx < k * k; idx += blockDim.x) {
-        const int j = idx / k, i = idx - j * k;
-        const perm_c128 v = A[i * k + j];
+    double *aneg = acol + 2 * k * kp;
+    double *x0 = aneg + 2 * k * kp;
+    for (int idx = threadIdx.x; idx < k * kp; idx += blockDim.x) {
+        const int j = idx / kp, i = idx - j * kp;
+        const perm_c128 v = i < k ? A[i * k + j] : perm_c128{0.0, 0.0};
         acol[2 * idx] = v.re;
         acol[2 * idx + 1] = v.im;
         aneg[2 * idx] = -v.re;
         aneg[2 * idx + 1] = -v.im;
+    }
+    for (int i = k + int(threadIdx.x); i < kp; i += blockDim.x) {
+        x0[2 * i] = 1.0;
+        x0[2 * i + 1] = 0.0;
     }
     for (int i = threadIdx.x; i < k; i += blockDim.x) {
         double sr = 0.0, er = 0.0, si = 0.0, ei = 0.0;
@@ -72,8 +80,9 @@ __device__ __forceinline__ void batched_item(const BatchMatDev &M, int w,
             }
         }
     } else {
-        const double *aneg = acol + 2 * K * K;
-        const double *x0 = aneg + 2 * K * K;
+        constexpr int KP = GradItemShape<K, true>::NP;
+        const double *aneg = acol + 2 * K * KP;
+        const double *x0 = aneg + 2 * K * KP;
         const uint64_t lanes_active = (uint64_t(1) << (K - 1)) >> M.c;
         grad_item<K, true>(acol, aneg, x0, uint64_t(w), M.c, M.r, lanes_active, perm_out, g_out,
                            want_grad, lds);
@@ -90,18 +99,20 @@ struct BatchDispatch {
     }
 };
 
-// Persistent kernel for the items of orders in [K0, K1].
+// Persistent loop for the items of orders in [K0, K1]: blocks of
+// kBatchThreads (the waves of one grad_item) take items from the counter.
 template <int K0, int K1>
-__global__ __launch_bounds__(kWave) void batched_persistent(
+__device__ __forceinline__ void persistent_items(
     const BatchMatDev *__restrict__ mats, const BatchItemDev *__restrict__ items, int64_t n_items,
     uint32_t *__restrict__ counter, const double *__restrict__ stage,
-    dd *__restrict__ perm_parts, dd *__restrict__ g_parts, int want_grad)
+    dd *__restrict__ perm_parts, dd *__restrict__ g_parts, int want_grad, double *lds,
+    uint32_t *next)
 {
-    __shared__ double lds[GradItemShape<K1, true>::LDS_DOUBLES];
     for (;;) {
-        uint32_t it = 0;
-        if (threadIdx.x == 0) it = atomicAdd(counter, 1u);
-        it = __builtin_amdgcn_readfirstlane(__shfl(it, 0, 64));
+        if (threadIdx.x == 0) *next = atomicAdd(counter, 1u);
+        __syncthreads();
+        const uint32_t it = __builtin_amdgcn_readfirstlane(*next);
+        __syncthreads();  // every wave has read `next` before it is overwritten
         if (int64_t(it) >= n_items) break;
         const BatchItemDev I = items[it];
         const BatchMatDev M = mats[I.m];
@@ -109,6 +120,36 @@ __global__ __launch_bounds__(kWave) void batched_persistent(
         dd *gp = g_parts + M.gbase + int64_t(I.w) * 2 * M.k * M.k;
         BatchDispatch<K0, K1>::run(M.k, M, I.w, stage, pp, gp, want_grad != 0, lds);
     }
+}
+
+// Orders up to 24 fit two waves per SIMD (at most 256 registers per lane)
+// without spilling; the compiler is held to that.
+template <int K0, int K1>
+__global__ __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(2))) void
+batched_persistent(const BatchMatDev *__restrict__ mats, const BatchItemDev *__restrict__ items,
+                   int64_t n_items, uint32_t *__restrict__ counter,
+                   const double *__restrict__ stage, dd *__restrict__ perm_parts,
+                   dd *__restrict__ g_parts, int want_grad)
+{
+    static_assert(GradItemShape<K1, true>::THREADS == kBatchThreads, "block shape");
+    __shared__ double lds[GradItemShape<K1, true>::LDS_DOUBLES];
+    __shared__ uint32_t next;
+    persistent_items<K0, K1>(mats, items, n_items, counter, stage, perm_parts, g_parts, want_grad,
+                             lds, &next);
+}
+
+// Orders 25..32 need more registers: one wave per SIMD.
+template <int K0, int K1>
+__global__ __launch_bounds__(kBatchThreads) void batched_persistent_large(
+    const BatchMatDev *__restrict__ mats, const BatchItemDev *__restrict__ items, int64_t n_items,
+    uint32_t *__restrict__ counter, const double *__restrict__ stage,
+    dd *__restrict__ perm_parts, dd *__restrict__ g_parts, int want_grad)
+{
+    static_assert(GradItemShape<K1, true>::THREADS == kBatchThreads, "block shape");
+    __shared__ double lds[GradItemShape<K1, true>::LDS_DOUBLES];
+    __shared__ uint32_t next;
+    persistent_items<K0, K1>(mats, items, n_items, counter, stage, perm_parts, g_parts, want_grad,
+                             lds, &next);
 }
 
 // One block per matrix: perm[m] = 2 (-1)^(k-1) sum of item partials, and
@@ -175,7 +216,7 @@ int launch_weighted_sum(int count, const double *wts, const perm_c128 *perms, pe
 static void launch_persistent(const BatchLaunch &L, int g, hipStream_t stream)
 {
     if (L.n_items[g] <= 0) return;
-    const dim3 grid(unsigned(L.grid[g])), block(kWave);
+    const dim3 grid(unsigned(L.grid[g])), block(kBatchThreads);
     const int64_t n = L.n_items[g];
     if (g == 0)
         hipLaunchKernelGGL((batched_persistent<1, 16>), grid, block, 0, stream, L.mats, L.items[0], n,
@@ -184,7 +225,7 @@ static void launch_persistent(const BatchLaunch &L, int g, hipStream_t stream)
         hipLaunchKernelGGL((batched_persistent<17, 24>), grid, block, 0, stream, L.mats, L.items[1], n,
                            L.counters + 1, L.stage, L.perm_parts, L.g_parts, L.want_grad);
     else
-        hipLaunchKernelGGL((batched_persistent<25, 32>), grid, block, 0, stream, L.mats, L.items[2], n,
+        hipLaunchKernelGGL((batched_persistent_large<25, 32>), grid, block, 0, stream, L.mats, L.items[2], n,
                            L.counters + 2, L.stage, L.perm_parts, L.g_parts, L.want_grad);
 }
 

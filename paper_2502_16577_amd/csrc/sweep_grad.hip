@@ -22,10 +22,44 @@
 
 namespace perm {
 
-constexpr int kGradBlock = 64;  // one wave per block
+constexpr int kGradBlock = 128;  // one grad_item (two waves) per block
 
-// Permanent (and, if asked, gradient) of one matrix: wave w = blockIdx.x.
-// perm_part[2w..2w+1] and g_part[w * W*N*N ...] receive the wave's shares.
+// Staging for grad_item: column-major +-A with np rows per column (rows >= n
+// zero) and x0 with np entries (1 for rows >= n).  A is row-major with W
+// doubles per entry and a row stride of lda entries.
+template <bool CPLX>
+__global__ __launch_bounds__(kBlock) void prep_grad(int n, int np, const double *__restrict__ A,
+                                                    int64_t lda, double *__restrict__ acol,
+                                                    double *__restrict__ aneg,
+                                                    double *__restrict__ x0)
+{
+    constexpr int W = CPLX ? 2 : 1;
+    for (int idx = threadIdx.x; idx < n * np; idx += blockDim.x) {
+        const int j = idx / np, i = idx - j * np;
+#pragma unroll
+        for (int q = 0; q < W; ++q) {
+            const double v = i < n ? A[(int64_t(i) * lda + j) * W + q] : 0.0;
+            acol[W * idx + q] = v;
+            aneg[W * idx + q] = -v;
+        }
+    }
+    for (int i = threadIdx.x; i < np; i += blockDim.x) {
+#pragma unroll
+        for (int q = 0; q < W; ++q) {
+            if (i >= n) {
+                x0[W * i + q] = q == 0 ? 1.0 : 0.0;
+                continue;
+            }
+            double s = 0.0, e = 0.0;  // compensated row sum
+            for (int j = 0; j < n; ++j) acc_add(s, e, A[(int64_t(i) * lda + j) * W + q]);
+            x0[W * i + q] = (A[(int64_t(i) * lda + n - 1) * W + q] - 0.5 * s) - 0.5 * e;
+        }
+    }
+}
+
+// Permanent (and, if asked, gradient) of one matrix: item w = blockIdx.x
+// (subsets 64 w .. 64 w + 63).  perm_part[2w..2w+1] and g_part[w * W*N*N ...]
+// receive the item's shares.
 template <int N, bool CPLX>
 __global__ __launch_bounds__(kGradBlock) void sweep_grad(const double *__restrict__ acol,
                                                          const double *__restrict__ aneg,
@@ -35,6 +69,7 @@ __global__ __launch_bounds__(kGradBlock) void sweep_grad(const double *__restric
                                                          int64_t lanes_active, int want_grad)
 {
     using S = GradItemShape<N, CPLX>;
+    static_assert(S::THREADS == kGradBlock, "block shape");
     __shared__ double lds[S::LDS_DOUBLES];
     const uint64_t w = blockIdx.x;
     grad_item<N, CPLX>(acol, aneg, x0, w, c, r, uint64_t(lanes_active), perm_part + 2 * w,
@@ -158,11 +193,12 @@ GradPlan plan_grad(int n)
 static int launch_stage(int n, bool cplx, const void *A, int64_t lda, double *acol, double *aneg,
                         double *x0, hipStream_t stream)
 {
+    const int np = grad_rows(n);
     if (cplx)
-        hipLaunchKernelGGL(prep_dense_c128, dim3(1), dim3(kBlock), 0, stream, n,
-                           static_cast<const perm_c128 *>(A), lda, acol, aneg, x0);
+        hipLaunchKernelGGL(prep_grad<true>, dim3(1), dim3(kBlock), 0, stream, n, np,
+                           static_cast<const double *>(A), lda, acol, aneg, x0);
     else
-        hipLaunchKernelGGL(prep_dense_f64, dim3(1), dim3(kBlock), 0, stream, n,
+        hipLaunchKernelGGL(prep_grad<false>, dim3(1), dim3(kBlock), 0, stream, n, np,
                            static_cast<const double *>(A), lda, acol, aneg, x0);
     return PERM_OK;
 }
