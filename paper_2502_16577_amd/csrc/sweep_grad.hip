@@ -5,19 +5,12 @@
 // sum of Algorithm 1 term by term gives
 //     dperm/da_kl = (-1)^(n-1) sum_g (-1)^g L_k(g) tau_l(g),
 //     L_k(g) = prod_{i != k} x_i(g)  (leave-one-out products).
-// Per subset the kernel forms L by a prefix and a suffix product pass (no
-// division, so zeros in x are harmless), and the rank-1 updates L tau^T of
-// the 64 subsets a wave holds at one step are one FP64 MFMA contraction:
-//     G (n x n) += V (n x 64) * T (64 x n),   V = L^T, T = (-1)^g tau,
-// as 16 x v_mfma_f64_16x16x4f64 per 16x16 output tile.  V goes through LDS
-// to get from lane-per-subset to the MFMA operand layout; T is computed in
-// registers from the Gray code of the subset each lane stands for.
-//
-// MFMA operand layout (gfx950, 64 lanes): A[i][k] at lane i + 16k,
-// B[k][j] at lane j + 16k, D[i][j] at lane j + 16 (i mod 4), register i / 4.
-// The MFMA accumulators are folded every 32 steps into per-wave double-double
-// accumulators in global memory, so plain FP64 accumulation never spans more
-// than 2048 terms.
+// Per subset the kernel forms L by prefix and suffix product passes (no
+// division, so zeros in x are harmless) and contracts V = (-1)^g L with tau
+// on FP64 MFMA, organised by Gray-code windows (grad_item.h).  Each block of
+// two waves covers 64 subsets; the waves split the rows.  The MFMA
+// accumulators are folded at the end of every window (at most 128 steps)
+// into per-item double-double accumulators in global memory.
 #include "grad_item.h"
 
 namespace perm {
