@@ -7,11 +7,10 @@
 namespace perm {
 
 constexpr int kBatchMaxK = 32;
-constexpr int kBatchThreads = 128;  // one grad_item (two waves) per block
+constexpr int kBatchThreads = kGradSlices * kWave;  // one grad_item per block
 
-// Staged rows per column of an order-k matrix (grad_item pads to an even
-// count so the two waves get equal row slices).
-__host__ __device__ inline int batch_rows(int k) { return k + (k & 1); }
+// Staged rows per column of an order-k matrix (grad_item's padding).
+__host__ __device__ inline int batch_rows(int k) { return grad_rows(k); }
 
 // One matrix of the batch.
 struct BatchMatDev {

@@ -1,9 +1,10 @@
 // One work item of the permanent-and-gradient sweep: 64 subsets (lane K =
 // 64 w + lane walks the Gray steps g in [K 2^c, (K+1) 2^c) of one matrix),
-// processed by a block of NS = 2 waves that split the matrix's rows: wave h
+// processed by a block of NS waves that split the matrix's rows: wave h
 // holds rows [h R, (h+1) R) of every subset's x, window sum and
-// leave-one-out products, so each wave keeps half the state in registers.
-// Once per step the waves swap the products of their halves through LDS.
+// leave-one-out products, so each wave keeps 1/NS of the state in
+// registers.  Once per step the waves swap the products of their slices
+// through LDS.
 // Shared by the single-matrix kernel (sweep_grad.hip) and the batched
 // persistent kernels (sweep_batched.hip).
 //
@@ -64,7 +65,7 @@ __device__ __forceinline__ void wave_sync_lds()
 
 template <int N, bool CPLX>
 struct GradItemShape {
-    static constexpr int NS = 2;                  // waves (row slices) per item
+    static constexpr int NS = kGradSlices;        // waves (row slices) per item
     static constexpr int R = (N + NS - 1) / NS;   // rows per slice (<= 16 for N <= 32)
     static constexpr int NP = NS * R;             // staged rows per column
     static constexpr int MT = (N + 15) / 16;      // 16-column tiles of G
@@ -202,14 +203,26 @@ __device__ __forceinline__ void grad_item(const double *__restrict__ acol,
             ei_[b] = fi;
             gmul<CPLX>(fr, fi, br[b], bi[b]);
         }
-        // the other slice's product, through LDS (the buffer alternates with
-        // the step parity, so one barrier per step suffices)
+        // the other slices' products, through LDS (the buffer alternates
+        // with the step parity, so one barrier per step suffices)
         double *xb = xbuf + int(l & 1u) * NS * kWave * W;
         xb[(h * kWave + lane) * W] = fr;
         if (CPLX) xb[(h * kWave + lane) * W + 1] = fi;
         __syncthreads();
-        const double orr = xb[((1 - h) * kWave + lane) * W];
-        const double oii = CPLX ? xb[((1 - h) * kWave + lane) * W + 1] : 0.0;
+        double orr, oii;
+        if constexpr (NS == 2) {
+            orr = xb[((1 - h) * kWave + lane) * W];
+            oii = CPLX ? xb[((1 - h) * kWave + lane) * W + 1] : 0.0;
+        } else {
+            orr = 1.0;
+            oii = 0.0;
+#pragma unroll
+            for (int s2 = 0; s2 < NS; ++s2) {
+                if (s2 == h) continue;
+                const double *xo = xb + (s2 * kWave + lane) * W;
+                gmul<CPLX>(orr, oii, xo[0], CPLX ? xo[1] : 0.0);
+            }
+        }
         if (h == 0) {  // the whole product, counted once per item
             double pr0 = fr, pi0 = fi;
             gmul<CPLX>(pr0, pi0, orr, oii);

@@ -45,14 +45,13 @@ DenseWs dense_ws_layout(int n, int components, int64_t blocks)
 {
     DenseWs L;
     size_t off = 0;
-    const size_t np = size_t(grad_rows(n));
-    const size_t nn = size_t(n) * np * size_t(components) * sizeof(double);
+    const size_t nn = size_t(n) * size_t(n) * size_t(components) * sizeof(double);
     L.acol = off;
     off += align256(nn);
     L.aneg = off;
     off += align256(nn);
     L.x0 = off;
-    off += align256(np * size_t(components) * sizeof(double));
+    off += align256(size_t(n) * size_t(components) * sizeof(double));
     L.partials = off;
     off += align256(size_t(std::max<int64_t>(blocks, 1)) * size_t(components) * sizeof(dd));
     L.total = off;

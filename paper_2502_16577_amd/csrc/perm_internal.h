@@ -140,8 +140,13 @@ struct GradWs {
 };
 
 GradWs grad_ws_layout(int n, int components, int64_t waves);
-// Staged rows per column for grad_item (padded to the two row slices).
-inline int grad_rows(int n) { return n + (n & 1); }
+// Waves per gradient work item; they split the matrix's rows (grad_item.h).
+constexpr int kGradSlices = 2;
+// Staged rows per column for grad_item: padded to a multiple of the slices.
+__host__ __device__ inline int grad_rows(int n)
+{
+    return (n + kGradSlices - 1) / kGradSlices * kGradSlices;
+}
 
 // ---------------------------------------------------------------------------
 // Kernel launchers (defined in the .hip files).  All return PERM_OK or

@@ -15,7 +15,7 @@
 
 namespace perm {
 
-constexpr int kGradBlock = 128;  // one grad_item (two waves) per block
+constexpr int kGradBlock = kGradSlices * kWave;  // one grad_item per block
 
 // Staging for grad_item: column-major +-A with np rows per column (rows >= n
 // zero) and x0 with np entries (1 for rows >= n).  A is row-major with W
