@@ -39,8 +39,8 @@ PEAK_FMA_TFLOPS = 78.6                           # published FP64 vector peak (F
 # plain 1 GiB copy (profiles/sweep_dense_f64_n32_u01.md).  Valid only for the
 # kernel source they were measured on; reported as null once it changes.
 COUNTERS_SRC = os.path.join(ROOT, "paper_2502_16577_amd", "csrc", "sweep_f64.hip")
-COUNTERS_SRC_SHA256 = "4cf2ce9695ee0e6196cd8c26bad56ab889c3636e56637db083a55de6695f85b1"
-TRAFFIC_BYTES_PER_LAUNCH = 186 * 1024 * 2.000 + 32 * 1024 * 1.000
+COUNTERS_SRC_SHA256 = "af6bb66dd995eb91518bc7f0bd7ad89e6283ccc6a6f47663b4fbe7513a6e9539"
+TRAFFIC_BYTES_PER_LAUNCH = 188 * 1024 * 2.000 + 32 * 1024 * 1.000
 
 
 def traffic_bytes():
