@@ -257,6 +257,16 @@ def bench_rows():
         dt = time.perf_counter() - t0
         line({"row": "a9 binary exact", "workload": name, "seconds": dt, "perm": str(val),
               "primes": len(res), "subset_steps_per_s": 2 ** (nb - 1) / dt})
+        # the same through the kernel generated for the pattern
+        t0 = time.perf_counter()
+        api.perm_binary_exact(a01, generated=True)
+        first = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        gval, gres = api.perm_binary_exact(a01, generated=True)
+        dt = time.perf_counter() - t0
+        line({"row": "a9 binary exact, generated kernel", "workload": name, "seconds": dt,
+              "first_call_seconds": first, "perm": str(gval), "equal": gval == val,
+              "subset_steps_per_s": 2 ** (nb - 1) / dt})
 
     # a10: perm + dperm/dA of one matrix
     for dtype, mat in (("f64", workloads.uniform(24, 1024)),

@@ -181,6 +181,22 @@ int perm_binary_exact(int n, const int32_t *col_ptr, const int32_t *row_idx,
                       uint64_t *out_residues, int *out_nprimes, void *ws,
                       size_t ws_bytes, void *stream);
 
+/* perm_binary_exact through a kernel generated for this 0/1 pattern (the
+ * per-matrix code generation of Section 3.3 applied to the exact path):
+ * columns are reordered by ascending count and the rows the four lowest
+ * columns touch are moved last; each flip is a fixed list of +-2 updates on
+ * the column's rows; inside a 16-step block the products of the other rows
+ * ("cold" rows) are computed once, and a block in which a cold row is zero
+ * for all 64 subsets of a wave is skipped whole (only its net flip of column
+ * 3 is applied).  The first call for a pattern on a device compiles the
+ * kernel with hiprtc and keeps it loaded until the process ends.  Same
+ * arguments, results, workspace (PERM_KIND_BINARY) and synchronisation as
+ * perm_binary_exact; n < 14 runs perm_binary_exact's own kernel.
+ * PERM_ECOMPILE if the compilation fails. */
+int perm_binary_exact_gen(int n, const int32_t *col_ptr, const int32_t *row_idx, int32_t nnz,
+                          int n_primes, uint64_t out_limbs[5], uint64_t *out_residues,
+                          int *out_nprimes, void *ws, size_t ws_bytes, void *stream);
+
 /* Element types for perm_grad. */
 #define PERM_DTYPE_F64  1
 #define PERM_DTYPE_C128 2

@@ -165,10 +165,12 @@ def _csc_of(a01):
     return n, col_ptr, np.array(rows, np.int32)
 
 
-def perm_binary_exact(a01=None, *, csc=None, n_primes: int = 0, device="cuda:0", ws=None):
+def perm_binary_exact(a01=None, *, csc=None, n_primes: int = 0, device="cuda:0", ws=None,
+                      generated: bool = False):
     """Exact permanent of a 0/1 matrix (dense 0/1 array or csc=(n, col_ptr, row_idx)).
 
-    Returns (value as Python int, list of residues perm mod p_k)."""
+    generated=True runs perm_binary_exact_gen (a kernel compiled for the
+    pattern).  Returns (value as Python int, list of residues perm mod p_k)."""
     if csc is None:
         n, col_ptr, row_idx = _csc_of(a01)
     else:
@@ -181,12 +183,13 @@ def perm_binary_exact(a01=None, *, csc=None, n_primes: int = 0, device="cuda:0",
     res = np.zeros(5, np.uint64)
     used = ctypes.c_int(0)
     nnz = int(row_idx.size)
-    st = N.lib().perm_binary_exact(
+    fn = N.lib().perm_binary_exact_gen if generated else N.lib().perm_binary_exact
+    st = fn(
         n, col_ptr.ctypes.data if n else None,
         row_idx.ctypes.data if nnz else None, nnz, n_primes,
         limbs.ctypes.data, res.ctypes.data, ctypes.byref(used), ws.data_ptr(), need,
         _stream(device))
-    N.check(st, "perm_binary_exact")
+    N.check(st, "perm_binary_exact_gen" if generated else "perm_binary_exact")
     value = 0
     for k in range(4, -1, -1):
         value = (value << 64) | int(limbs[k])

@@ -341,9 +341,12 @@ int perm_sparse_f64_gen(int n, const int32_t *col_ptr, const int32_t *row_idx,
                              out, base, st);
 }
 
-int perm_binary_exact(int n, const int32_t *col_ptr, const int32_t *row_idx, int32_t nnz,
-                      int n_primes, uint64_t out_limbs[5], uint64_t *out_residues,
-                      int *out_nprimes, void *ws, size_t ws_bytes, void *stream)
+// The exact binary path; `generated` selects the kernel generated for the
+// pattern (n >= kSparseGenMinN) instead of the staged one.
+static int binary_exact(int n, const int32_t *col_ptr, const int32_t *row_idx, int32_t nnz,
+                        int n_primes, uint64_t out_limbs[5], uint64_t *out_residues,
+                        int *out_nprimes, void *ws, size_t ws_bytes, void *stream,
+                        bool generated)
 {
     if (!valid_n(n) || !out_limbs || n_primes < 0 || n_primes > kMaxPrimes) return PERM_EINVAL;
     if (n > 0 && !valid_csc(n, col_ptr, row_idx, nnz)) return PERM_EINVAL;
@@ -384,6 +387,44 @@ int perm_binary_exact(int n, const int32_t *col_ptr, const int32_t *row_idx, int
     const int w = check_ws(ws, ws_bytes, L.total);
     if (w != PERM_OK) return w;
 
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char *base = static_cast<char *>(ws);
+    uint64_t *res_dev = reinterpret_cast<uint64_t *>(base + L.residues);
+    int rc = PERM_OK;
+    if (generated && n >= kSparseGenMinN) {
+        // Columns by ascending count (the low columns flip most often and the
+        // densest is the never-flipped last one); rows that columns 0..3 do
+        // not touch first ("cold": constant inside a 16-step block).
+        std::vector<int> col(n);
+        for (int j = 0; j < n; ++j) col[j] = j;
+        std::stable_sort(col.begin(), col.end(), [&](int x, int y) { return csum[x] < csum[y]; });
+        std::vector<char> hot(n, 0);
+        for (int jn = 0; jn < 4; ++jn)
+            for (int i = 0; i < n; ++i) hot[i] = hot[i] || dense[size_t(i) * n + col[jn]] != 0.0;
+        std::vector<int> row;
+        for (int i = 0; i < n; ++i)
+            if (!hot[i]) row.push_back(i);
+        const int n_cold = int(row.size());
+        for (int i = 0; i < n; ++i)
+            if (hot[i]) row.push_back(i);
+        std::vector<double> pd(size_t(n) * n);
+        std::vector<std::vector<int>> rows(n);
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                pd[size_t(i) * n + j] = dense[size_t(row[i]) * n + col[j]];
+                if (pd[size_t(i) * n + j] != 0.0) rows[j].push_back(i);
+            }
+        if (hipMemcpyAsync(base + L.dense01, pd.data(), pd.size() * sizeof(double),
+                           hipMemcpyHostToDevice, st) != hipSuccess)
+            return PERM_EHIP;
+        rc = launch_binary_gen(n, n_cold, rows, reinterpret_cast<const double *>(base + L.dense01),
+                               np, res_dev, base, st);
+        if (rc != PERM_OK) {
+            hipStreamSynchronize(st);  // the staging buffer must outlive the copy
+            return rc;
+        }
+        if (hipStreamSynchronize(st) != hipSuccess) return PERM_EHIP;
+    } else {
     // Zero-block skipping plan (the permanent is invariant under row and
     // column permutations): columns by ascending count, so the fast-flipping
     // low columns touch few rows and the densest column is the never-flipped
@@ -438,15 +479,16 @@ int perm_binary_exact(int n, const int32_t *col_ptr, const int32_t *row_idx, int
         dense.swap(perm_dense);
     }
 
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    char *base = static_cast<char *>(ws);
     if (hipMemcpyAsync(base + L.dense01, dense.data(), dense.size() * sizeof(double),
                        hipMemcpyHostToDevice, st) != hipSuccess)
         return PERM_EHIP;
-    uint64_t *res_dev = reinterpret_cast<uint64_t *>(base + L.residues);
-    const int rc = launch_binary_residues(n, reinterpret_cast<const double *>(base + L.dense01),
-                                          np, skip_b, nfrozen, res_dev, base, st);
-    if (rc != PERM_OK) return rc;
+    rc = launch_binary_residues(n, reinterpret_cast<const double *>(base + L.dense01), np, skip_b,
+                                nfrozen, res_dev, base, st);
+    if (rc != PERM_OK) {
+        hipStreamSynchronize(st);  // the staging buffer must outlive the copy
+        return rc;
+    }
+    }
     uint64_t R[kMaxPrimes] = {0, 0, 0, 0, 0};
     if (hipMemcpyAsync(R, res_dev, sizeof(uint64_t) * np, hipMemcpyDeviceToHost, st) != hipSuccess)
         return PERM_EHIP;
@@ -488,6 +530,22 @@ int perm_binary_exact(int n, const int32_t *col_ptr, const int32_t *row_idx, int
     }
     for (int q = 0; q < 5; ++q) out_limbs[q] = limbs[q];
     return PERM_OK;
+}
+
+int perm_binary_exact(int n, const int32_t *col_ptr, const int32_t *row_idx, int32_t nnz,
+                      int n_primes, uint64_t out_limbs[5], uint64_t *out_residues,
+                      int *out_nprimes, void *ws, size_t ws_bytes, void *stream)
+{
+    return binary_exact(n, col_ptr, row_idx, nnz, n_primes, out_limbs, out_residues, out_nprimes,
+                        ws, ws_bytes, stream, false);
+}
+
+int perm_binary_exact_gen(int n, const int32_t *col_ptr, const int32_t *row_idx, int32_t nnz,
+                          int n_primes, uint64_t out_limbs[5], uint64_t *out_residues,
+                          int *out_nprimes, void *ws, size_t ws_bytes, void *stream)
+{
+    return binary_exact(n, col_ptr, row_idx, nnz, n_primes, out_limbs, out_residues, out_nprimes,
+                        ws, ws_bytes, stream, true);
 }
 
 int perm_grad(int n, int dtype, const void *A, int64_t lda, void *out_perm, void *out_grad,

@@ -160,6 +160,14 @@ constexpr int kSparseGenMinN = 14;
 int launch_sparse_gen(int n, const std::vector<std::vector<int>> &rows, const double *dense_dev,
                       double *out, char *ws, hipStream_t stream);
 std::string sparse_gen_source(int n, const std::vector<std::vector<int>> &rows);
+// Exact binary sweep through a kernel generated for the pattern: rows are
+// ordered with the n_cold rows that columns 0..3 do not touch first, `rows`
+// as above; writes the nprimes residues of sum_g (-1)^g prod y to
+// residues_dev (binary workspace layout).
+int launch_binary_gen(int n, int n_cold, const std::vector<std::vector<int>> &rows,
+                      const double *dense01_dev, int nprimes, uint64_t *residues_dev, char *ws,
+                      hipStream_t stream);
+std::string binary_gen_source(int n, int n_cold, const std::vector<std::vector<int>> &rows);
 
 int launch_dense_f64(int n, const double *A, int64_t lda, double *out, char *ws,
                      hipStream_t stream);

@@ -173,6 +173,208 @@ std::string kernel_source(int n, const std::vector<std::vector<int>> &rows)
     return o.str();
 }
 
+// ---- exact binary sweep (y = 2x, residues modulo primes 2^61 - c) -------
+
+// Rows per exactly representable group product: |y_i| <= n <= 2^bits.
+int binary_group_rows(int n)
+{
+    const int bits = n <= 2 ? 1 : n <= 4 ? 2 : n <= 8 ? 3 : n <= 16 ? 4 : n <= 32 ? 5 : 6;
+    return 53 / bits;
+}
+
+const char *kBinaryPrelude = R"(
+typedef unsigned int u32;
+typedef unsigned long long u64;
+__device__ inline u64 reduce61(unsigned __int128 x, u64 c, u64 p)
+{
+    const u64 m61 = (u64(1) << 61) - 1;
+    const u64 lo = u64(x) & m61;
+    const unsigned __int128 hi = x >> 61;
+    const unsigned __int128 y = hi * c + lo;
+    const u64 lo2 = u64(y) & m61;
+    const u64 hi2 = u64(y >> 61);
+    u64 z = lo2 + hi2 * c;
+    if (z >= p) z -= p;
+    return z;
+}
+__device__ inline u64 mulmod61(u64 a, u64 b, u64 c, u64 p) { return reduce61((unsigned __int128)a * b, c, p); }
+__device__ inline u64 addmod(u64 a, u64 b, u64 p) { const u64 s = a + b; return s >= p ? s - p : s; }
+__device__ inline u64 exact_u64(double v)
+{
+    const double hi = __builtin_trunc(v * 0x1p-32);
+    const double lo = __builtin_fma(-hi, 0x1p32, v);
+    return (u64(u32(hi)) << 32) | u64(u32(lo));
+}
+__device__ inline void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+__device__ inline u32 gray_low(u32 l, u32 kb, int c)
+{ u32 g = l ^ (l >> 1) ^ (kb << (c - 1)); return g & ((1u << c) - 1u); }
+)";
+
+// Column j's update on y: +2 / -2 on its rows, or + f (a lane's 0 / 2).
+std::string ycolumn_code(const std::vector<std::vector<int>> &rows, int j, char op)
+{
+    std::ostringstream o;
+    for (int r : rows[j]) {
+        if (op == '+') o << "y" << r << " += 2.0; ";
+        else if (op == '-') o << "y" << r << " -= 2.0; ";
+        else o << "y" << r << " += f; ";
+    }
+    return o.str();
+}
+
+std::string yswitch_code(int n, const std::vector<std::vector<int>> &rows, char op)
+{
+    std::ostringstream o;
+    o << "switch (j) {\n";
+    for (int j = 0; j < n - 1; ++j) {
+        if (rows[j].empty()) continue;
+        o << "case " << j << ": " << ycolumn_code(rows, j, op) << "break;\n";
+    }
+    o << "default: break;\n}\n";
+    return o.str();
+}
+
+// Group products: cold rows [0, n_cold) and hot rows [n_cold, n) are grouped
+// separately (G rows per group), so the cold groups stay constant inside a
+// 16-step block.  Returns the expressions; *m_cold = number of cold groups.
+std::vector<std::string> group_exprs(int n, int n_cold, int *m_cold)
+{
+    const int G = binary_group_rows(n);
+    std::vector<std::string> g;
+    auto add_range = [&](int a, int b) {
+        for (int s = a; s < b; s += G) {
+            std::ostringstream o;
+            o << "(";
+            for (int i = s; i < std::min(b, s + G); ++i) o << (i > s ? " * " : "") << "y" << i;
+            o << ")";
+            g.push_back(o.str());
+        }
+    };
+    add_range(0, n_cold);
+    *m_cold = int(g.size());
+    add_range(n_cold, n);
+    return g;
+}
+
+std::string binary_kernel_source(int n, int n_cold, const std::vector<std::vector<int>> &rows)
+{
+    int m_cold = 0;
+    const std::vector<std::string> grp = group_exprs(n, n_cold, &m_cold);
+    const int M = int(grp.size());
+    std::ostringstream o;
+    o << kBinaryPrelude;
+    o << "#define M " << M << "\n#define QCAP 128\n";
+    o << "extern \"C\" __global__ __launch_bounds__(256) void perm_binary_gen(\n"
+         "    const double *__restrict__ ys, u64 *__restrict__ partials, int c, int nprimes)\n{\n"
+         "    const u64 kC[5] = {1, 31, 45, 229, 259};\n"
+         "    __shared__ double queue[4][M * QCAP];\n"
+         "    __shared__ u64 red[4][5];\n"
+         "    const u32 lane = threadIdx.x & 63u;\n"
+         "    const u32 wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);\n"
+         "    const u64 wave = u64(blockIdx.x) * 4 + wib;\n"
+         "    const u64 K = (wave & 1u) | (u64(lane) << 1) | ((wave >> 1) << 7);\n"
+         "    const u32 kb = u32(wave & 1u);\n"
+         "    const u64 g0 = K << c;\n"
+         "    const u64 hbits = (g0 ^ (g0 >> 1)) >> c;\n"
+         "    const u32 C = 1u << c;\n"
+         "    double *q = queue[wib];\n";
+    o << "    double";
+    for (int i = 0; i < n; ++i) o << (i ? ", " : " ") << "y" << i;
+    o << ";\n";
+    for (int i = 0; i < n; ++i) o << "    y" << i << " = ys[" << i << "];\n";
+    // exact seed of the chunk start (integers: no drift, no re-seeding)
+    o << "    for (int j = c; j < " << n - 1 << "; ++j) {\n"
+         "        const double f = ((hbits >> (j - c)) & 1u) ? 2.0 : 0.0;\n        "
+      << yswitch_code(n, rows, 'f') << "    }\n"
+      << "    {\n        u32 low = gray_low(0, kb, c);\n"
+         "        while (low) {\n            const int j = __builtin_ctz(low);\n"
+         "            low &= low - 1u;\n            "
+      << yswitch_code(n, rows, '+') << "        }\n    }\n";
+    o << "    u64 acc[5] = {0, 0, 0, 0, 0};\n    u32 count = 0;\n";
+    // drain one queue entry into the residues
+    o << "    auto drain = [&](int slot) {\n"
+         "        bool neg = false;\n        u64 a[M];\n"
+         "#pragma unroll\n        for (int m = 0; m < M; ++m) {\n"
+         "            double v = q[m * QCAP + slot];\n"
+         "            if (v < 0.0) { neg = !neg; v = -v; }\n"
+         "            a[m] = exact_u64(v);\n        }\n"
+         "#pragma unroll\n        for (int k = 0; k < 5; ++k) {\n"
+         "            if (k < nprimes) {\n"
+         "                const u64 cc = kC[k];\n                const u64 p = (u64(1) << 61) - cc;\n"
+         "                u64 P = a[0];\n"
+         "#pragma unroll\n                for (int m = 1; m < M; ++m) P = mulmod61(P, a[m], cc, p);\n"
+         "                acc[k] = addmod(acc[k], (neg && P) ? p - P : P, p);\n"
+         "            }\n        }\n    };\n";
+    // push the current term if it is nonzero
+    o << "    auto push = [&](bool negative) {\n        double gp[M];\n";
+    for (int m = 0; m < M; ++m) o << "        gp[" << m << "] = " << grp[m] << ";\n";
+    o << "        bool nz = true;\n"
+         "#pragma unroll\n        for (int m = 0; m < M; ++m) nz = nz && (gp[m] != 0.0);\n"
+         "        if (negative) gp[0] = -gp[0];\n"
+         "        const u64 ballot = __ballot(nz);\n"
+         "        if (ballot == 0) return;\n"
+         "        const u32 before = __builtin_amdgcn_mbcnt_hi(u32(ballot >> 32), __builtin_amdgcn_mbcnt_lo(u32(ballot), 0u));\n"
+         "        if (nz) {\n            const u32 slot = count + before;\n"
+         "#pragma unroll\n            for (int m = 0; m < M; ++m) q[m * QCAP + slot] = gp[m];\n        }\n"
+         "        count += u32(__builtin_popcountll(ballot));\n"
+         "        if (count >= 64) {\n            wave_sync();\n"
+         "            drain(int(count - 64 + lane));\n            count -= 64;\n            wave_sync();\n"
+         "        }\n    };\n";
+    // the walk in 16-step blocks
+    o << "    for (u32 l = 0; l < C; l += 16u) {\n"
+         "        if (l != 0) {\n            const int j = __builtin_ctz(l);\n"
+         "            if ((gray_low(l, kb, c) >> j) & 1u) {\n"
+      << yswitch_code(n, rows, '+') << "            } else {\n"
+      << yswitch_code(n, rows, '-') << "            }\n        }\n";
+    if (m_cold > 0) {
+        // cold rows do not change inside the block: if one is zero for every
+        // lane, all 16 terms are zero and only the flip of column 3 remains
+        o << "        bool cold_nz = true;\n";
+        for (int m = 0; m < m_cold; ++m) o << "        cold_nz = cold_nz && (" << grp[m] << " != 0.0);\n";
+        o << "        if (__ballot(cold_nz) == 0) {\n"
+             "            if ((l >> 4) & 1u) { " << ycolumn_code(rows, 3, '-') << "} else { "
+          << ycolumn_code(rows, 3, '+') << "}\n            continue;\n        }\n";
+    }
+    // the 16 steps of the block as a loop with one push site (the push and
+    // its modular drain are long; sixteen inlined copies would not fit the
+    // instruction cache); the cold rows are not written inside the loop, so
+    // their group products are computed once per block
+    o << "        for (u32 m = 0; m < 16u; ++m) {\n"
+         "            switch (m) {\n";
+    for (int m = 1; m < 16; ++m) {
+        const int j = __builtin_ctz(unsigned(m));
+        o << "            case " << m << ": ";
+        if (j + 1 < kGenUnroll) {
+            const bool neg = (m >> (j + 1)) & 1;
+            o << ycolumn_code(rows, j, neg ? '-' : '+');
+        } else {
+            o << "if ((l >> 4) & 1u) { " << ycolumn_code(rows, j, '-') << "} else { "
+              << ycolumn_code(rows, j, '+') << "} ";
+        }
+        o << "break;\n";
+    }
+    o << "            default: break;\n            }\n"
+         "            push((m & 1u) != 0u);\n        }\n    }\n";
+    // what is left in the queue, then the modular reductions
+    o << "    wave_sync();\n    if (lane < count) drain(int(lane));\n"
+         "#pragma unroll\n    for (int k = 0; k < 5; ++k) {\n"
+         "        if (k < nprimes) {\n            const u64 p = (u64(1) << 61) - kC[k];\n"
+         "            u64 v = acc[k];\n"
+         "#pragma unroll\n            for (int off = 32; off >= 1; off >>= 1) v = addmod(v, __shfl_xor(v, off, 64), p);\n"
+         "            if (lane == 0) red[wib][k] = v;\n        }\n    }\n"
+         "    __syncthreads();\n"
+         "    if (threadIdx.x < u32(nprimes)) {\n        const int k = int(threadIdx.x);\n"
+         "        const u64 p = (u64(1) << 61) - kC[k];\n        u64 v = 0;\n"
+         "        for (int w = 0; w < 4; ++w) v = addmod(v, red[w][k], p);\n"
+         "        partials[u64(blockIdx.x) * nprimes + k] = v;\n    }\n}\n";
+    return o.str();
+}
+
 struct GenModule {
     hipModule_t mod = nullptr;
     hipFunction_t fn = nullptr;
@@ -181,12 +383,14 @@ struct GenModule {
 std::mutex g_mu;
 std::unordered_map<std::string, GenModule> g_cache;
 
-std::string cache_key(int dev, int n, const std::vector<std::vector<int>> &rows)
+std::string cache_key(int kind, int dev, int n, int extra, const std::vector<std::vector<int>> &rows)
 {
     std::string k;
     auto put = [&](int v) { k.append(reinterpret_cast<const char *>(&v), sizeof(v)); };
+    put(kind);
     put(dev);
     put(n);
+    put(extra);
     for (const auto &c : rows) {
         put(int(c.size()));
         for (int r : c) put(r);
@@ -194,11 +398,10 @@ std::string cache_key(int dev, int n, const std::vector<std::vector<int>> &rows)
     return k;
 }
 
-int compile_module(int n, const std::vector<std::vector<int>> &rows, GenModule &out)
+int compile_module(const std::string &src, const char *name, GenModule &out)
 {
-    const std::string src = kernel_source(n, rows);
     hiprtcProgram prog;
-    if (hiprtcCreateProgram(&prog, src.c_str(), "perm_sparse_gen.hip", 0, nullptr, nullptr) !=
+    if (hiprtcCreateProgram(&prog, src.c_str(), "perm_generated.hip", 0, nullptr, nullptr) !=
         HIPRTC_SUCCESS)
         return PERM_ECOMPILE;
     const char *opts[] = {"--offload-arch=gfx950", "-O3", "-Xclang", "-target-feature",
@@ -213,7 +416,26 @@ int compile_module(int n, const std::vector<std::vector<int>> &rows, GenModule &
     hiprtcDestroyProgram(&prog);
     if (code.empty()) return PERM_ECOMPILE;
     if (hipModuleLoadData(&out.mod, code.data()) != hipSuccess) return PERM_EHIP;
-    if (hipModuleGetFunction(&out.fn, out.mod, "perm_sparse_gen") != hipSuccess) return PERM_EHIP;
+    if (hipModuleGetFunction(&out.fn, out.mod, name) != hipSuccess) return PERM_EHIP;
+    return PERM_OK;
+}
+
+// The module for (kind, device, pattern), compiled on first use.
+int get_module(int kind, int n, int extra, const std::vector<std::vector<int>> &rows,
+               const std::string &src_if_new, const char *name, GenModule &m)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return PERM_EHIP;
+    std::lock_guard<std::mutex> lock(g_mu);
+    const std::string key = cache_key(kind, dev, n, extra, rows);
+    auto it = g_cache.find(key);
+    if (it != g_cache.end()) {
+        m = it->second;
+        return PERM_OK;
+    }
+    const int rc = compile_module(src_if_new, name, m);
+    if (rc != PERM_OK) return rc;
+    g_cache.emplace(key, m);
     return PERM_OK;
 }
 
@@ -228,20 +450,10 @@ int launch_sparse_gen(int n, const std::vector<std::vector<int>> &rows, const do
                       double *out, char *ws, hipStream_t stream)
 {
     if (n < kSparseGenMinN || n > PERM_MAX_N) return PERM_EUNSUPPORTED;
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return PERM_EHIP;
     GenModule m;
     {
-        std::lock_guard<std::mutex> lock(g_mu);
-        const std::string key = cache_key(dev, n, rows);
-        auto it = g_cache.find(key);
-        if (it == g_cache.end()) {
-            const int rc = compile_module(n, rows, m);
-            if (rc != PERM_OK) return rc;
-            g_cache.emplace(key, m);
-        } else {
-            m = it->second;
-        }
+        const int rc = get_module(0, n, 0, rows, kernel_source(n, rows), "perm_sparse_gen", m);
+        if (rc != PERM_OK) return rc;
     }
     const SweepPlan p = plan_sweep(n, 0);
     const DenseWs L = dense_ws_layout(n, 1, dense_ws_blocks(n));
@@ -275,6 +487,48 @@ int launch_sparse_gen(int n, const std::vector<std::vector<int>> &rows, const do
     const double scale = (n & 1) ? 2.0 : -2.0;  // 2 (-1)^(n-1)
     hipLaunchKernelGGL(finalize_partials, dim3(1), dim3(kBlock), 0, stream, partials, p.blocks, 1,
                        scale, out);
+    return hipGetLastError() == hipSuccess ? PERM_OK : PERM_EHIP;
+}
+
+}  // namespace perm
+
+namespace perm {
+
+std::string binary_gen_source(int n, int n_cold, const std::vector<std::vector<int>> &rows)
+{
+    return binary_kernel_source(n, n_cold, rows);
+}
+
+int launch_binary_gen(int n, int n_cold, const std::vector<std::vector<int>> &rows,
+                      const double *dense01_dev, int nprimes, uint64_t *residues_dev, char *ws,
+                      hipStream_t stream)
+{
+    if (n < kSparseGenMinN || n > PERM_MAX_N) return PERM_EUNSUPPORTED;
+    GenModule m;
+    {
+        const int rc = get_module(1, n, n_cold, rows, binary_kernel_source(n, n_cold, rows),
+                                  "perm_binary_gen", m);
+        if (rc != PERM_OK) return rc;
+    }
+    const SweepPlan p = plan_sweep(n, 0);
+    const BinaryWs L = binary_ws_layout(n, p.blocks);
+    double *ycol = reinterpret_cast<double *>(ws + L.ycol);
+    double *yneg = reinterpret_cast<double *>(ws + L.yneg);
+    double *y0 = reinterpret_cast<double *>(ws + L.y0);
+    uint64_t *partials = reinterpret_cast<uint64_t *>(ws + L.partials);
+    hipLaunchKernelGGL(prep_binary, dim3(1), dim3(kBlock), 0, stream, n, dense01_dev, ycol, yneg,
+                       y0);
+    {
+        const double *y_arg = y0;
+        uint64_t *p_arg = partials;
+        int c_arg = p.log2_chunk, np_arg = nprimes;
+        void *args[] = {&y_arg, &p_arg, &c_arg, &np_arg};
+        if (hipModuleLaunchKernel(m.fn, unsigned(p.blocks), 1, 1, kBlock, 1, 1, 0, stream, args,
+                                  nullptr) != hipSuccess)
+            return PERM_EHIP;
+    }
+    hipLaunchKernelGGL(finalize_residues, dim3(1), dim3(kBlock), 0, stream, partials, p.blocks,
+                       nprimes, residues_dev);
     return hipGetLastError() == hipSuccess ? PERM_OK : PERM_EHIP;
 }
 

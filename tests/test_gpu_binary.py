@@ -93,3 +93,46 @@ def test_full_size_sparse40():
     got, res = api.perm_binary_exact(a)
     assert got == int(g["value"])
     check_residues(got, res)
+
+
+# Kernels generated for the pattern (perm_binary_exact_gen): the same exact
+# values, on random patterns against the oracle, closed forms and both
+# full-size inputs.
+@pytest.mark.parametrize("n,per_row", [(14, 3), (17, 4), (21, 5), (24, 6)])
+def test_generated_sparse_rows(oracle, n, per_row):
+    a = W.sparse_rows(n, per_row, 1900 + n)
+    got, res = api.perm_binary_exact(a, generated=True)
+    assert got == oracle.binary(a), n
+    check_residues(got, res)
+
+
+@pytest.mark.parametrize("n", [14, 19, 24])
+def test_generated_bernoulli_and_closed_forms(oracle, n):
+    a = W.bernoulli(n, 1950 + n)
+    assert api.perm_binary_exact(a, generated=True)[0] == oracle.binary(a)
+    assert api.perm_binary_exact(np.ones((n, n), np.uint8), generated=True)[0] == math.factorial(n)
+    assert api.perm_binary_exact(W.ones_minus_identity(n).astype(np.uint8),
+                                 generated=True)[0] == derangements(n)
+    assert api.perm_binary_exact(W.tridiagonal_ones(n).astype(np.uint8),
+                                 generated=True)[0] == fib(n + 1)
+    assert api.perm_binary_exact(W.block_ones(n, 2 if n % 2 == 0 else 1).astype(np.uint8),
+                                 generated=True)[0] == (2 if n % 2 == 0 else 1) ** (n // (2 if n % 2 == 0 else 1))
+
+
+def test_generated_small_and_empty():
+    a = W.bernoulli(10, 7)  # below the generated path's minimum order: the staged kernel
+    assert api.perm_binary_exact(a, generated=True)[0] == api.perm_binary_exact(a)[0]
+    b = W.bernoulli(16, 2)
+    b[:, 5] = 0
+    assert api.perm_binary_exact(b, generated=True)[0] == 0
+
+
+@pytest.mark.parametrize("name", ["bernoulli32", "sparse40"])
+def test_generated_full_size(name):
+    g = _golden(name)
+    a = (W.bernoulli(32, W.SEED_BERNOULLI32) if name == "bernoulli32"
+         else W.sparse_rows(40, 6, W.SEED_SPARSE40))
+    assert W.digest(a) == g["digest"]
+    got, res = api.perm_binary_exact(a, generated=True)
+    assert got == int(g["value"]), name
+    check_residues(got, res)
