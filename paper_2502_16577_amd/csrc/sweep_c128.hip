@@ -46,6 +46,32 @@ __device__ __forceinline__ void cmul(double &ar, double &ai, double br, double b
     ai = i;
 }
 
+// Eight interleaved chains (more independent work per step) where the
+// registers allow it (n <= 30); four above.
+template <int N>
+__device__ __forceinline__ void cproduct8(const double (&xr)[N], const double (&xi)[N],
+                                          double &outr, double &outi)
+{
+    static_assert(N >= 8, "cproduct8 needs N >= 8");
+    double r[8], im[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        r[c] = xr[c];
+        im[c] = xi[c];
+    }
+#pragma unroll
+    for (int i = 8; i < N; ++i) cmul(r[i & 7], im[i & 7], xr[i], xi[i]);
+    cmul(r[0], im[0], r[1], im[1]);
+    cmul(r[2], im[2], r[3], im[3]);
+    cmul(r[4], im[4], r[5], im[5]);
+    cmul(r[6], im[6], r[7], im[7]);
+    cmul(r[0], im[0], r[2], im[2]);
+    cmul(r[4], im[4], r[6], im[6]);
+    cmul(r[0], im[0], r[4], im[4]);
+    outr = r[0];
+    outi = im[0];
+}
+
 template <int N>
 __device__ __forceinline__ void cproduct4(const double (&xr)[N], const double (&xi)[N],
                                           double &outr, double &outi)
@@ -65,6 +91,14 @@ __device__ __forceinline__ void cproduct4(const double (&xr)[N], const double (&
     cmul(r0, i0, r2, i2);
     outr = r0;
     outi = i0;
+}
+
+template <int N>
+__device__ __forceinline__ void cproduct(const double (&xr)[N], const double (&xi)[N],
+                                         double &outr, double &outi)
+{
+    if constexpr (N <= 30) cproduct8<N>(xr, xi, outr, outi);
+    else cproduct4<N>(xr, xi, outr, outi);
 }
 
 template <int N>
@@ -143,7 +177,7 @@ __global__ __launch_bounds__(kBlock) void sweep_dense_c128(const double *__restr
             add_ccolumn<N>(xr, xi, (add ? acol : aneg) + 2 * j * N);
         }
         double br, bi;
-        cproduct4<N>(xr, xi, br, bi);
+        cproduct<N>(xr, xi, br, bi);
 #pragma unroll
         for (uint32_t m = 1; m < B; ++m) {
             const int j = __builtin_ctz(m);
@@ -155,7 +189,7 @@ __global__ __launch_bounds__(kBlock) void sweep_dense_c128(const double *__restr
             asm volatile("" : "+s"(zero));
             add_ccolumn<N>(xr, xi, (neg ? aneg : acol) + 2 * j * N + zero);
             double tr, ti;
-            cproduct4<N>(xr, xi, tr, ti);
+            cproduct<N>(xr, xi, tr, ti);
             if (m & 1u) {  // (-1)^g = (-1)^m since l is even
                 br -= tr;
                 bi -= ti;
