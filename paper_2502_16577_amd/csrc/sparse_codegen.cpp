@@ -8,15 +8,18 @@
 // so matrices with the same pattern share one module).
 //
 // The generated kernel walks each lane's chunk in 16-step blocks exactly as
-// the dense sweep does (one column chosen at run time per block, the other
-// fifteen flips compile-time columns 0..3 with signs fixed by the step within
-// the block), re-seeds exactly every 2^r steps, accumulates block sums by
-// two-sum and writes one double-double partial per block.
+// the dense sweep does (one column chosen at run time per block, read whole
+// from the staged copy; the other fifteen flips are compile-time columns
+// 0..3 with signs fixed by the step within the block), re-seeds exactly
+// every 2^r steps, accumulates block sums by two-sum and writes one
+// double-double partial per block.  The exact binary variant below works the
+// same way on y = 2x with residues modulo primes.
 #include <hip/hip_runtime.h>
 #include <hip/hiprtc.h>
 
 #include <algorithm>
 #include <cstring>
+#include <functional>
 #include <mutex>
 #include <sstream>
 #include <string>
@@ -75,15 +78,17 @@ std::string column_code(int n, const std::vector<std::vector<int>> &rows, int j,
     return o.str();
 }
 
-std::string switch_code(int n, const std::vector<std::vector<int>> &rows, const char *var, char op)
+
+// Update of every row by a run-time column `col` (wave-uniform pointer into
+// the staged column-major copy): straight-line code, so no register copies
+// are needed where control flow merges.  op: '+' adds, 'f' adds f * col.
+std::string dense_column_code(int n, const char *var, char op)
 {
     std::ostringstream o;
-    o << "switch (" << var << ") {\n";
-    for (int j = 0; j < n - 1; ++j) {
-        if (rows[j].empty()) continue;
-        o << "case " << j << ": " << column_code(n, rows, j, op) << "break;\n";
+    for (int i = 0; i < n; ++i) {
+        if (op == '+') o << var << i << " += col[" << i << "]; ";
+        else o << var << i << " = __builtin_fma(f, col[" << i << "], " << var << i << "); ";
     }
-    o << "default: break;\n}\n";
     return o.str();
 }
 
@@ -113,8 +118,8 @@ std::string kernel_source(int n, const std::vector<std::vector<int>> &rows)
     std::ostringstream o;
     o << kPrelude;
     o << "extern \"C\" __global__ __launch_bounds__(256) void perm_sparse_gen(\n"
-         "    const double *__restrict__ a, const double *__restrict__ xs, dd *__restrict__ partials,\n"
-         "    int c, int r, u32 l_begin, u32 l_end, int accumulate)\n{\n"
+         "    const double *__restrict__ a, const double *__restrict__ an, const double *__restrict__ xs,\n"
+         "    dd *__restrict__ partials, int c, int r, u32 l_begin, u32 l_end, int accumulate)\n{\n"
          "    __shared__ dd red[4];\n"
          "    const u32 lane = threadIdx.x & 63u;\n"
          "    const u64 wave = u64(blockIdx.x) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);\n"
@@ -129,24 +134,25 @@ std::string kernel_source(int n, const std::vector<std::vector<int>> &rows)
     o << "    for (u32 l = l_begin; l < l_end; l += 16u) {\n"
          "        if ((l & rmask) == 0) {\n";
     for (int i = 0; i < n; ++i) o << "            x" << i << " = xs[" << i << "];\n";
+    // re-seed and the block's first (run-time) flip read whole staged
+    // columns; only the compile-time flips below use the nonzero lists
     o << "            for (int j = c; j < " << n - 1 << "; ++j) {\n"
          "                const double f = ((hbits >> (j - c)) & 1u) ? 1.0 : 0.0;\n"
-         "                "
-      << switch_code(n, rows, "j", 'f')
-      << "            }\n"
+         "                const double *col = a + j * " << n << ";\n                "
+      << dense_column_code(n, "x", 'f')
+      << "\n            }\n"
          "            u32 low = gray_low(l, kb, c);\n"
          "            while (low) {\n"
          "                const int j = __builtin_ctz(low);\n"
          "                low &= low - 1u;\n"
-         "                "
-      << switch_code(n, rows, "j", '+')
-      << "            }\n"
+         "                const double *col = a + j * " << n << ";\n                "
+      << dense_column_code(n, "x", '+')
+      << "\n            }\n"
          "        } else {\n"
          "            const int j = __builtin_ctz(l);\n"
-         "            if ((gray_low(l, kb, c) >> j) & 1u) {\n"
-      << switch_code(n, rows, "j", '+') << "            } else {\n"
-      << switch_code(n, rows, "j", '-') << "            }\n"
-         "        }\n";
+         "            const double *col = (((gray_low(l, kb, c) >> j) & 1u) ? a : an) + j * " << n << ";\n"
+         "            "
+      << dense_column_code(n, "x", '+') << "\n        }\n";
     const std::string prod = product_code(n);
     o << "        double t0 = " << prod << ";\n";
     const int B = 1 << kGenUnroll;
@@ -227,17 +233,6 @@ std::string ycolumn_code(const std::vector<std::vector<int>> &rows, int j, char 
     return o.str();
 }
 
-std::string yswitch_code(int n, const std::vector<std::vector<int>> &rows, char op)
-{
-    std::ostringstream o;
-    o << "switch (j) {\n";
-    for (int j = 0; j < n - 1; ++j) {
-        if (rows[j].empty()) continue;
-        o << "case " << j << ": " << ycolumn_code(rows, j, op) << "break;\n";
-    }
-    o << "default: break;\n}\n";
-    return o.str();
-}
 
 // Group products: cold rows [0, n_cold) and hot rows [n_cold, n) are grouped
 // separately (G rows per group), so the cold groups stay constant inside a
@@ -246,14 +241,14 @@ std::vector<std::string> group_exprs(int n, int n_cold, int *m_cold)
 {
     const int G = binary_group_rows(n);
     std::vector<std::string> g;
+    // a balanced product tree (short dependency chains; any order is exact)
+    std::function<std::string(int, int)> tree = [&](int a, int b) -> std::string {
+        if (b - a == 1) return "y" + std::to_string(a);
+        const int mid = a + (b - a) / 2;
+        return "(" + tree(a, mid) + " * " + tree(mid, b) + ")";
+    };
     auto add_range = [&](int a, int b) {
-        for (int s = a; s < b; s += G) {
-            std::ostringstream o;
-            o << "(";
-            for (int i = s; i < std::min(b, s + G); ++i) o << (i > s ? " * " : "") << "y" << i;
-            o << ")";
-            g.push_back(o.str());
-        }
+        for (int s = a; s < b; s += G) g.push_back(tree(s, std::min(b, s + G)));
     };
     add_range(0, n_cold);
     *m_cold = int(g.size());
@@ -270,7 +265,8 @@ std::string binary_kernel_source(int n, int n_cold, const std::vector<std::vecto
     o << kBinaryPrelude;
     o << "#define M " << M << "\n#define QCAP 128\n";
     o << "extern \"C\" __global__ __launch_bounds__(256) void perm_binary_gen(\n"
-         "    const double *__restrict__ ys, u64 *__restrict__ partials, int c, int nprimes)\n{\n"
+         "    const double *__restrict__ yc, const double *__restrict__ yn, const double *__restrict__ ys,\n"
+         "    u64 *__restrict__ partials, int c, int nprimes)\n{\n"
          "    const u64 kC[5] = {1, 31, 45, 229, 259};\n"
          "    __shared__ double queue[4][M * QCAP];\n"
          "    __shared__ u64 red[4][5];\n"
@@ -289,12 +285,14 @@ std::string binary_kernel_source(int n, int n_cold, const std::vector<std::vecto
     for (int i = 0; i < n; ++i) o << "    y" << i << " = ys[" << i << "];\n";
     // exact seed of the chunk start (integers: no drift, no re-seeding)
     o << "    for (int j = c; j < " << n - 1 << "; ++j) {\n"
-         "        const double f = ((hbits >> (j - c)) & 1u) ? 2.0 : 0.0;\n        "
-      << yswitch_code(n, rows, 'f') << "    }\n"
+         "        const double f = ((hbits >> (j - c)) & 1u) ? 1.0 : 0.0;\n"
+         "        const double *col = yc + j * " << n << ";\n        "
+      << dense_column_code(n, "y", 'f') << "\n    }\n"
       << "    {\n        u32 low = gray_low(0, kb, c);\n"
          "        while (low) {\n            const int j = __builtin_ctz(low);\n"
-         "            low &= low - 1u;\n            "
-      << yswitch_code(n, rows, '+') << "        }\n    }\n";
+         "            low &= low - 1u;\n"
+         "            const double *col = yc + j * " << n << ";\n            "
+      << dense_column_code(n, "y", '+') << "\n        }\n    }\n";
     o << "    u64 acc[5] = {0, 0, 0, 0, 0};\n    u32 count = 0;\n";
     // drain one queue entry into the residues
     o << "    auto drain = [&](int slot) {\n"
@@ -328,14 +326,14 @@ std::string binary_kernel_source(int n, int n_cold, const std::vector<std::vecto
     // the walk in 16-step blocks
     o << "    for (u32 l = 0; l < C; l += 16u) {\n"
          "        if (l != 0) {\n            const int j = __builtin_ctz(l);\n"
-         "            if ((gray_low(l, kb, c) >> j) & 1u) {\n"
-      << yswitch_code(n, rows, '+') << "            } else {\n"
-      << yswitch_code(n, rows, '-') << "            }\n        }\n";
+         "            const double *col = (((gray_low(l, kb, c) >> j) & 1u) ? yc : yn) + j * " << n << ";\n"
+         "            " << dense_column_code(n, "y", '+') << "\n        }\n";
     if (m_cold > 0) {
         // cold rows do not change inside the block: if one is zero for every
         // lane, all 16 terms are zero and only the flip of column 3 remains
+        // (bitwise &: no short-circuit branches)
         o << "        bool cold_nz = true;\n";
-        for (int m = 0; m < m_cold; ++m) o << "        cold_nz = cold_nz && (" << grp[m] << " != 0.0);\n";
+        for (int m = 0; m < m_cold; ++m) o << "        cold_nz = cold_nz & (" << grp[m] << " != 0.0);\n";
         o << "        if (__ballot(cold_nz) == 0) {\n"
              "            if ((l >> 4) & 1u) { " << ycolumn_code(rows, 3, '-') << "} else { "
           << ycolumn_code(rows, 3, '+') << "}\n            continue;\n        }\n";
@@ -474,12 +472,13 @@ int launch_sparse_gen(int n, const std::vector<std::vector<int>> &rows, const do
     span = std::min(pow2, C);
     for (int64_t l0 = 0; l0 < C; l0 += span) {
         const double *a_arg = acol;
+        const double *an_arg = aneg;
         const double *x_arg = x0;
         dd *p_arg = partials;
         int c_arg = c, r_arg = r;
         uint32_t lb = uint32_t(l0), le = uint32_t(l0 + span);
         int acc = l0 > 0;
-        void *args[] = {&a_arg, &x_arg, &p_arg, &c_arg, &r_arg, &lb, &le, &acc};
+        void *args[] = {&a_arg, &an_arg, &x_arg, &p_arg, &c_arg, &r_arg, &lb, &le, &acc};
         if (hipModuleLaunchKernel(m.fn, unsigned(p.blocks), 1, 1, kBlock, 1, 1, 0, stream, args,
                                   nullptr) != hipSuccess)
             return PERM_EHIP;
@@ -519,10 +518,12 @@ int launch_binary_gen(int n, int n_cold, const std::vector<std::vector<int>> &ro
     hipLaunchKernelGGL(prep_binary, dim3(1), dim3(kBlock), 0, stream, n, dense01_dev, ycol, yneg,
                        y0);
     {
+        const double *yc_arg = ycol;
+        const double *yn_arg = yneg;
         const double *y_arg = y0;
         uint64_t *p_arg = partials;
         int c_arg = p.log2_chunk, np_arg = nprimes;
-        void *args[] = {&y_arg, &p_arg, &c_arg, &np_arg};
+        void *args[] = {&yc_arg, &yn_arg, &y_arg, &p_arg, &c_arg, &np_arg};
         if (hipModuleLaunchKernel(m.fn, unsigned(p.blocks), 1, 1, kBlock, 1, 1, 0, stream, args,
                                   nullptr) != hipSuccess)
             return PERM_EHIP;
