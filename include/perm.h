@@ -305,6 +305,11 @@ int perm_decomp_info(const perm_decomp *d, int *count, int *max_order, int64_t *
                      int64_t *removed_nonzeros);
 /* Leaf idx: order, weight and (if data is non-NULL) its k*k entries. */
 int perm_decomp_leaf(const perm_decomp *d, int idx, int *k, double *weight, double *data);
+/* All leaves at once (host arrays of perm_decomp_info's count, any may be
+ * NULL): k[i], weight[i], offset[i] = element offset of leaf i in data, and
+ * data = the leaves' row-major entries back to back (total_elements). */
+int perm_decomp_leaves(const perm_decomp *d, int32_t *k, double *weight, int64_t *offset,
+                       double *data);
 void perm_decomp_destroy(perm_decomp *d);
 
 /* The k-th prime used by perm_binary_exact (k = 0..4), 0 if out of range. */

@@ -321,12 +321,9 @@ DECOMP_DM = 1
 DECOMP_FM = 2
 
 
-def decompose(n: int, col_ptr, row_idx, vals, flags: int = DECOMP_DM | DECOMP_FM,
-              min_leaf: int = 0):
-    """Section 4 preprocessing on the host (no GPU work).
-
-    Returns (leaves, removed) with leaves = [(weight, k x k float64 array)]:
-    perm(A) = sum weight * perm(leaf); an empty list means perm = 0."""
+def _decompose_arrays(n: int, col_ptr, row_idx, vals, flags: int, min_leaf: int):
+    """perm_decompose + perm_decomp_leaves: (k int32[L], weight float64[L],
+    offset int64[L], data float64[total], removed)."""
     col_ptr = np.ascontiguousarray(col_ptr, dtype=np.int32)
     row_idx = np.ascontiguousarray(row_idx, dtype=np.int32)
     vals = np.ascontiguousarray(vals, dtype=np.float64)
@@ -340,17 +337,28 @@ def decompose(n: int, col_ptr, row_idx, vals, flags: int = DECOMP_DM | DECOMP_FM
         tot, rem = ctypes.c_int64(), ctypes.c_int64()
         N.check(L.perm_decomp_info(h, ctypes.byref(cnt), ctypes.byref(mx), ctypes.byref(tot),
                                    ctypes.byref(rem)), "perm_decomp_info")
-        leaves = []
-        for i in range(cnt.value):
-            k, w = ctypes.c_int(), ctypes.c_double()
-            N.check(L.perm_decomp_leaf(h, i, ctypes.byref(k), ctypes.byref(w), None),
-                    "perm_decomp_leaf")
-            m = np.zeros((k.value, k.value))
-            N.check(L.perm_decomp_leaf(h, i, None, None, m.ctypes.data), "perm_decomp_leaf")
-            leaves.append((w.value, m))
-        return leaves, rem.value
+        ks = np.zeros(cnt.value, np.int32)
+        ws = np.zeros(cnt.value, np.float64)
+        offs = np.zeros(cnt.value, np.int64)
+        data = np.zeros(max(tot.value, 1), np.float64)
+        if cnt.value:
+            N.check(L.perm_decomp_leaves(h, ks.ctypes.data, ws.ctypes.data, offs.ctypes.data,
+                                         data.ctypes.data), "perm_decomp_leaves")
+        return ks, ws, offs, data, rem.value
     finally:
         L.perm_decomp_destroy(h)
+
+
+def decompose(n: int, col_ptr, row_idx, vals, flags: int = DECOMP_DM | DECOMP_FM,
+              min_leaf: int = 0):
+    """Section 4 preprocessing on the host (no GPU work).
+
+    Returns (leaves, removed) with leaves = [(weight, k x k float64 array)]:
+    perm(A) = sum weight * perm(leaf); an empty list means perm = 0."""
+    ks, ws, offs, data, removed = _decompose_arrays(n, col_ptr, row_idx, vals, flags, min_leaf)
+    leaves = [(float(ws[i]), data[offs[i]:offs[i] + ks[i] * ks[i]].reshape(ks[i], ks[i]))
+              for i in range(len(ks))]
+    return leaves, removed
 
 
 def perm_sparse_decomp(n: int, col_ptr, row_idx, vals, flags: int = DECOMP_DM | DECOMP_FM,
@@ -360,30 +368,32 @@ def perm_sparse_decomp(n: int, col_ptr, row_idx, vals, flags: int = DECOMP_DM | 
     leaves, and a double-double weighted sum on the GPU.  Returns a 0-d
     float64 device tensor."""
     device = torch.device(device)
-    leaves, _ = decompose(n, col_ptr, row_idx, vals, flags)
+    ks, ws, offs, data, _ = _decompose_arrays(n, col_ptr, row_idx, vals, flags, 0)
     out = torch.zeros((), dtype=torch.complex128, device=device)
-    if not leaves:
+    if len(ks) == 0:
         return out.real.clone()
-    from .workloads import pack
-    small = [i for i, (_, m) in enumerate(leaves) if m.shape[0] <= 32]
-    big = [i for i, (_, m) in enumerate(leaves) if m.shape[0] > 32]
-    order = small + big
-    perms = torch.zeros(len(leaves), dtype=torch.complex128, device=device)
+    small = np.nonzero(ks <= 32)[0]
+    big = np.nonzero(ks > 32)[0]
+    order = np.concatenate([small, big])
+    perms = torch.zeros(len(ks), dtype=torch.complex128, device=device)
     keep = []
-    if small:
-        ks, offs, data = pack([leaves[i][1].astype(np.complex128) for i in small])
-        plan = BatchedPlan(ks, offs, want_grad=False, device=device)
-        d = torch.from_numpy(data).to(device)
+    if len(small):
+        # the batched kernels take complex entries: every leaf's entries as
+        # complex, back to back as the decomposition returned them
+        d = torch.from_numpy(data).to(device).to(torch.complex128)
+        plan = BatchedPlan(ks[small], offs[small], want_grad=False, device=device)
         plan.run(d, out=perms[:len(small)], use_graph=False)
         keep += [plan, d]
-    if big:  # orders above the batched limit: one dense launch each
+    if len(big):  # orders above the batched limit: one dense launch each
         pv = perms.view(torch.float64)
         for t, i in enumerate(big):
-            A = torch.from_numpy(np.ascontiguousarray(leaves[i][1])).to(device)
+            k = int(ks[i])
+            A = torch.from_numpy(np.ascontiguousarray(data[offs[i]:offs[i] + k * k].reshape(k, k)))
+            A = A.to(device)
             perm_dense_f64(A, out=pv[2 * (len(small) + t)])
             keep.append(A)
-    w = torch.tensor([leaves[i][0] for i in order], dtype=torch.float64, device=device)
-    N.check(N.lib().perm_weighted_sum(len(leaves), w.data_ptr(), perms.data_ptr(), out.data_ptr(),
+    w = torch.from_numpy(np.ascontiguousarray(ws[order])).to(device)
+    N.check(N.lib().perm_weighted_sum(len(ks), w.data_ptr(), perms.data_ptr(), out.data_ptr(),
                                       _stream(device)), "perm_weighted_sum")
     torch.cuda.current_stream(device).synchronize()  # keep plan / weights alive until done
     return out.real.clone()

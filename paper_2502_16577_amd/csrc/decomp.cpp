@@ -334,6 +334,23 @@ int perm_decomp_leaf(const perm_decomp *d, int idx, int *k, double *weight, doub
     return PERM_OK;
 }
 
+int perm_decomp_leaves(const perm_decomp *d, int32_t *k, double *weight, int64_t *offset,
+                       double *data)
+{
+    if (!d) return PERM_EINVAL;
+    int64_t off = 0;
+    for (size_t i = 0; i < d->leaves.size(); ++i) {
+        const Leaf &L = d->leaves[i];
+        if (k) k[i] = L.m.n;
+        if (weight) weight[i] = L.weight;
+        if (offset) offset[i] = off;
+        if (data && !L.m.a.empty())
+            std::memcpy(data + off, L.m.a.data(), L.m.a.size() * sizeof(double));
+        off += int64_t(L.m.n) * L.m.n;
+    }
+    return PERM_OK;
+}
+
 void perm_decomp_destroy(perm_decomp *d) { delete d; }
 
 }  // extern "C"
