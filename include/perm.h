@@ -164,12 +164,13 @@ int perm_sparse_f64_gen(int n, const int32_t *col_ptr, const int32_t *row_idx,
 /*
  * Exact permanent of a 0/1 matrix given by its nonzero pattern in CSC (the
  * number of perfect matchings of its bipartite graph, Section 1).  The sweep
- * runs on y = 2x, which is integral, modulo n_primes primes just below 2^61;
+ * runs on y = 2x, which is integral, modulo n_primes primes just above 2^50
+ * (perm_binary_prime), with the modular products done in FP64 arithmetic;
  * the residues are combined by Chinese remaindering on the host.
  *   col_ptr, row_idx  host CSC pattern as for perm_sparse_f64
- *   n_primes          0 = choose from the Bregman bound (at least 3), else 1..5
+ *   n_primes          0 = choose from the Bregman bound (at least 3), else 1..6
  *   out_limbs         host uint64[5]: perm as unsigned little-endian 320 bits
- *   out_residues      host uint64[5] or NULL: perm mod p_k for the primes
+ *   out_residues      host uint64[6] or NULL: perm mod p_k for the primes
  *                     used, zero in the unused slots
  *   out_nprimes       host int or NULL: number of primes used
  * Synchronises `stream`.  PERM_ERANGE if the bound exceeds the modulus of
@@ -312,7 +313,8 @@ int perm_decomp_leaves(const perm_decomp *d, int32_t *k, double *weight, int64_t
                        double *data);
 void perm_decomp_destroy(perm_decomp *d);
 
-/* The k-th prime used by perm_binary_exact (k = 0..4), 0 if out of range. */
+/* The k-th prime used by perm_binary_exact (k = 0..5; the six smallest
+ * primes above 2^50), 0 if out of range. */
 uint64_t perm_binary_prime(int k);
 
 #ifdef __cplusplus

@@ -180,7 +180,7 @@ def perm_binary_exact(a01=None, *, csc=None, n_primes: int = 0, device="cuda:0",
     device = torch.device(device)
     ws, need = _workspace(N.KIND_BINARY, n, 0, device, ws)
     limbs = np.zeros(5, np.uint64)
-    res = np.zeros(5, np.uint64)
+    res = np.zeros(6, np.uint64)
     used = ctypes.c_int(0)
     nnz = int(row_idx.size)
     fn = N.lib().perm_binary_exact_gen if generated else N.lib().perm_binary_exact

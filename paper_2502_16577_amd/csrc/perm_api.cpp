@@ -41,6 +41,24 @@ SweepPlan plan_sweep(int n, int /*steps_per_op_hint*/)
     return p;
 }
 
+SweepPlan plan_binary(int n)
+{
+    SweepPlan p = plan_sweep(n, 0);
+    if (n <= 12) return p;
+    // 2^20 lanes (4096 waves, 16 per SIMD) instead of 2^18: a lane's work
+    // depends on how many of its terms are nonzero, and with more, shorter
+    // chunks the waves that finish early are replaced by new ones
+    const int total = n - 1;
+    const int cmin = std::min(6, total - 8);
+    const int c = std::max(cmin, total - 20);
+    if (c >= p.log2_chunk || c > 31) return p;
+    p.log2_chunk = c;
+    p.log2_reseed = std::min(9, c);
+    p.lanes = int64_t(1) << (total - c);
+    p.blocks = p.lanes / kBlock;
+    return p;
+}
+
 DenseWs dense_ws_layout(int n, int components, int64_t blocks)
 {
     DenseWs L;
@@ -100,10 +118,7 @@ GradWs grad_ws_layout(int n, int components, int64_t waves)
     return L;
 }
 
-// Host copy of the primes 2^61 - c used by the binary kernels.
-constexpr uint64_t kPrimeCHost[kMaxPrimes] = {1, 31, 45, 229, 259};
-
-uint64_t host_prime(int k) { return (uint64_t(1) << 61) - kPrimeCHost[k]; }
+uint64_t host_prime(int k) { return kBinaryPrimes[k]; }
 
 }  // namespace perm
 
@@ -208,7 +223,7 @@ size_t perm_workspace_bytes(int kind, int n, int64_t m)
         return grad_ws_layout(n, kind == PERM_KIND_GRAD_C128 ? 2 : 1, p.waves).total;
     }
     case PERM_KIND_BINARY: {
-        const SweepPlan p = plan_sweep(n, 0);
+        const SweepPlan p = plan_binary(n);
         return binary_ws_layout(n, p.blocks).total;
     }
     default: return 0;
@@ -375,14 +390,15 @@ static int binary_exact(int n, const int32_t *col_ptr, const int32_t *row_idx, i
     int needed = 3;
     if (!empty_line) {
         const double bits = bregman_log2(rsum) + 1.0;  // +1: margin for rounding of the bound
-        while (needed < kMaxPrimes && double(needed) * 60.99 < bits) ++needed;
-        if (double(needed) * 60.99 < bits) return PERM_ERANGE;
+        // every prime exceeds 2^50, so `needed` primes hold 50 * needed bits
+        while (needed < kMaxPrimes && double(needed) * 50.0 < bits) ++needed;
+        if (double(needed) * 50.0 < bits) return PERM_ERANGE;
     }
     const int np = n_primes == 0 ? needed : n_primes;
     if (np < needed && !empty_line) return PERM_ERANGE;
     if (out_nprimes) *out_nprimes = np;
     if (empty_line) return PERM_OK;  // an empty row or column: no perfect matching
-    const SweepPlan plan = plan_sweep(n, 0);
+    const SweepPlan plan = plan_binary(n);
     const BinaryWs L = binary_ws_layout(n, plan.blocks);
     const int w = check_ws(ws, ws_bytes, L.total);
     if (w != PERM_OK) return w;
@@ -489,7 +505,7 @@ static int binary_exact(int n, const int32_t *col_ptr, const int32_t *row_idx, i
         return rc;
     }
     }
-    uint64_t R[kMaxPrimes] = {0, 0, 0, 0, 0};
+    uint64_t R[kMaxPrimes] = {};
     if (hipMemcpyAsync(R, res_dev, sizeof(uint64_t) * np, hipMemcpyDeviceToHost, st) != hipSuccess)
         return PERM_EHIP;
     if (hipStreamSynchronize(st) != hipSuccess) return PERM_EHIP;

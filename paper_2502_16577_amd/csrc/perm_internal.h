@@ -19,7 +19,7 @@ namespace perm {
 constexpr int kBlock = 256;          // threads per block: 4 waves of 64
 constexpr int kWave = 64;
 constexpr int kWavesPerBlock = kBlock / kWave;
-constexpr int kMaxPrimes = 5;        // binary path: at most 5 primes of 61 bits
+constexpr int kMaxPrimes = 6;        // binary path: at most 6 primes of 51 bits
 constexpr int kSmallN = 12;          // n <= 12: forward sweeps run on the one-wave gradient kernel
 
 // Gray-walk decomposition of the 2^(n-1) steps of one matrix:
@@ -34,6 +34,32 @@ struct SweepPlan {
 };
 
 SweepPlan plan_sweep(int n, int steps_per_op_hint);
+// The exact binary sweep's plan: the same walk with 4x more lanes (n > 12).
+SweepPlan plan_binary(int n);
+
+// Primes of the exact binary path: the six smallest primes above 2^50.  A
+// residue, and the product of two residues divided by p, fit the 53-bit
+// significand, so the kernels multiply modulo p in FP64 arithmetic: two
+// error-free products and a rounded quotient (no 64-bit integer multiplies).
+constexpr uint64_t kBinaryPrimes[kMaxPrimes] = {
+    1125899906842679ull, 1125899906842723ull, 1125899906842769ull,
+    1125899906842783ull, 1125899906842817ull, 1125899906842829ull};
+
+// The primes as kernel arguments: p exactly, and 1/p rounded to nearest.
+struct BinaryPrimes {
+    double p[kMaxPrimes];
+    double pinv[kMaxPrimes];
+};
+
+inline BinaryPrimes binary_primes()
+{
+    BinaryPrimes P;
+    for (int k = 0; k < kMaxPrimes; ++k) {
+        P.p[k] = double(kBinaryPrimes[k]);
+        P.pinv[k] = 1.0 / P.p[k];
+    }
+    return P;
+}
 
 // Run-time options of the dense real sweep.
 constexpr int kAccTwoSum = 0, kAccPlain = 1, kAccKahan = 2;  // lane accumulation modes

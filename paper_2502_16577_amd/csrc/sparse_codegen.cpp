@@ -179,38 +179,42 @@ std::string kernel_source(int n, const std::vector<std::vector<int>> &rows)
     return o.str();
 }
 
-// ---- exact binary sweep (y = 2x, residues modulo primes 2^61 - c) -------
+// ---- exact binary sweep (y = 2x, residues modulo primes just above 2^50) --
 
-// Rows per exactly representable group product: |y_i| <= n <= 2^bits.
+// Rows per group: |y_i| <= n <= 2^bits, so a group product is at most 2^50,
+// below every prime (an exact integer and already a residue).
 int binary_group_rows(int n)
 {
     const int bits = n <= 2 ? 1 : n <= 4 ? 2 : n <= 8 ? 3 : n <= 16 ? 4 : n <= 32 ? 5 : 6;
-    return 53 / bits;
+    return 50 / bits;
 }
 
+// Same arithmetic as the staged binary kernel: signed residues in doubles,
+// a * b mod p by an error-free product and a rounded quotient (exact for
+// |a|, |b| <= p, p in (2^50, 2^50 + 2^40)); contraction off so that exactly
+// these operations are emitted.
 const char *kBinaryPrelude = R"(
 typedef unsigned int u32;
 typedef unsigned long long u64;
-__device__ inline u64 reduce61(unsigned __int128 x, u64 c, u64 p)
+struct BinaryPrimes { double p[6]; double pinv[6]; };
+__device__ inline double mulmod50(double a, double b, double p, double pinv)
 {
-    const u64 m61 = (u64(1) << 61) - 1;
-    const u64 lo = u64(x) & m61;
-    const unsigned __int128 hi = x >> 61;
-    const unsigned __int128 y = hi * c + lo;
-    const u64 lo2 = u64(y) & m61;
-    const u64 hi2 = u64(y >> 61);
-    u64 z = lo2 + hi2 * c;
-    if (z >= p) z -= p;
-    return z;
+#pragma clang fp contract(off)
+    const double h = a * b;
+    const double l = __builtin_fma(a, b, -h);
+    const double q = __builtin_rint(h * pinv);
+    const double qh = q * p;
+    const double ql = __builtin_fma(q, p, -qh);
+    return (h - qh) + (l - ql);
 }
-__device__ inline u64 mulmod61(u64 a, u64 b, u64 c, u64 p) { return reduce61((unsigned __int128)a * b, c, p); }
+__device__ inline double addmod50(double acc, double t, double p, double pinv)
+{
+#pragma clang fp contract(off)
+    const double s = acc + t;
+    return __builtin_fma(-__builtin_rint(s * pinv), p, s);
+}
+__device__ inline u64 residue_u64(double v, double p) { return u64(v < 0.0 ? v + p : v); }
 __device__ inline u64 addmod(u64 a, u64 b, u64 p) { const u64 s = a + b; return s >= p ? s - p : s; }
-__device__ inline u64 exact_u64(double v)
-{
-    const double hi = __builtin_trunc(v * 0x1p-32);
-    const double lo = __builtin_fma(-hi, 0x1p32, v);
-    return (u64(u32(hi)) << 32) | u64(u32(lo));
-}
 __device__ inline void wave_sync()
 {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -266,10 +270,9 @@ std::string binary_kernel_source(int n, int n_cold, const std::vector<std::vecto
     o << "#define M " << M << "\n#define QCAP 128\n";
     o << "extern \"C\" __global__ __launch_bounds__(256) void perm_binary_gen(\n"
          "    const double *__restrict__ yc, const double *__restrict__ yn, const double *__restrict__ ys,\n"
-         "    u64 *__restrict__ partials, int c, int nprimes)\n{\n"
-         "    const u64 kC[5] = {1, 31, 45, 229, 259};\n"
+         "    u64 *__restrict__ partials, int c, int nprimes, const BinaryPrimes P)\n{\n"
          "    __shared__ double queue[4][M * QCAP];\n"
-         "    __shared__ u64 red[4][5];\n"
+         "    __shared__ u64 red[4][6];\n"
          "    const u32 lane = threadIdx.x & 63u;\n"
          "    const u32 wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);\n"
          "    const u64 wave = u64(blockIdx.x) * 4 + wib;\n"
@@ -293,20 +296,15 @@ std::string binary_kernel_source(int n, int n_cold, const std::vector<std::vecto
          "            low &= low - 1u;\n"
          "            const double *col = yc + j * " << n << ";\n            "
       << dense_column_code(n, "y", '+') << "\n        }\n    }\n";
-    o << "    u64 acc[5] = {0, 0, 0, 0, 0};\n    u32 count = 0;\n";
+    o << "    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};\n    u32 count = 0;\n";
     // drain one queue entry into the residues
-    o << "    auto drain = [&](int slot) {\n"
-         "        bool neg = false;\n        u64 a[M];\n"
-         "#pragma unroll\n        for (int m = 0; m < M; ++m) {\n"
-         "            double v = q[m * QCAP + slot];\n"
-         "            if (v < 0.0) { neg = !neg; v = -v; }\n"
-         "            a[m] = exact_u64(v);\n        }\n"
-         "#pragma unroll\n        for (int k = 0; k < 5; ++k) {\n"
+    o << "    auto drain = [&](int slot) {\n        double g[M];\n"
+         "#pragma unroll\n        for (int m = 0; m < M; ++m) g[m] = q[m * QCAP + slot];\n"
+         "#pragma unroll\n        for (int k = 0; k < 6; ++k) {\n"
          "            if (k < nprimes) {\n"
-         "                const u64 cc = kC[k];\n                const u64 p = (u64(1) << 61) - cc;\n"
-         "                u64 P = a[0];\n"
-         "#pragma unroll\n                for (int m = 1; m < M; ++m) P = mulmod61(P, a[m], cc, p);\n"
-         "                acc[k] = addmod(acc[k], (neg && P) ? p - P : P, p);\n"
+         "                double t = g[0];\n"
+         "#pragma unroll\n                for (int m = 1; m < M; ++m) t = mulmod50(t, g[m], P.p[k], P.pinv[k]);\n"
+         "                acc[k] = addmod50(acc[k], t, P.p[k], P.pinv[k]);\n"
          "            }\n        }\n    };\n";
     // push the current term if it is nonzero
     o << "    auto push = [&](bool negative) {\n        double gp[M];\n";
@@ -360,14 +358,14 @@ std::string binary_kernel_source(int n, int n_cold, const std::vector<std::vecto
          "            push((m & 1u) != 0u);\n        }\n    }\n";
     // what is left in the queue, then the modular reductions
     o << "    wave_sync();\n    if (lane < count) drain(int(lane));\n"
-         "#pragma unroll\n    for (int k = 0; k < 5; ++k) {\n"
-         "        if (k < nprimes) {\n            const u64 p = (u64(1) << 61) - kC[k];\n"
-         "            u64 v = acc[k];\n"
+         "#pragma unroll\n    for (int k = 0; k < 6; ++k) {\n"
+         "        if (k < nprimes) {\n            const u64 p = u64(P.p[k]);\n"
+         "            u64 v = residue_u64(acc[k], P.p[k]);\n"
          "#pragma unroll\n            for (int off = 32; off >= 1; off >>= 1) v = addmod(v, __shfl_xor(v, off, 64), p);\n"
          "            if (lane == 0) red[wib][k] = v;\n        }\n    }\n"
          "    __syncthreads();\n"
          "    if (threadIdx.x < u32(nprimes)) {\n        const int k = int(threadIdx.x);\n"
-         "        const u64 p = (u64(1) << 61) - kC[k];\n        u64 v = 0;\n"
+         "        const u64 p = u64(P.p[k]);\n        u64 v = 0;\n"
          "        for (int w = 0; w < 4; ++w) v = addmod(v, red[w][k], p);\n"
          "        partials[u64(blockIdx.x) * nprimes + k] = v;\n    }\n}\n";
     return o.str();
@@ -509,7 +507,7 @@ int launch_binary_gen(int n, int n_cold, const std::vector<std::vector<int>> &ro
                                   "perm_binary_gen", m);
         if (rc != PERM_OK) return rc;
     }
-    const SweepPlan p = plan_sweep(n, 0);
+    const SweepPlan p = plan_binary(n);
     const BinaryWs L = binary_ws_layout(n, p.blocks);
     double *ycol = reinterpret_cast<double *>(ws + L.ycol);
     double *yneg = reinterpret_cast<double *>(ws + L.yneg);
@@ -523,13 +521,14 @@ int launch_binary_gen(int n, int n_cold, const std::vector<std::vector<int>> &ro
         const double *y_arg = y0;
         uint64_t *p_arg = partials;
         int c_arg = p.log2_chunk, np_arg = nprimes;
-        void *args[] = {&yc_arg, &yn_arg, &y_arg, &p_arg, &c_arg, &np_arg};
+        BinaryPrimes pr_arg = binary_primes();
+        void *args[] = {&yc_arg, &yn_arg, &y_arg, &p_arg, &c_arg, &np_arg, &pr_arg};
         if (hipModuleLaunchKernel(m.fn, unsigned(p.blocks), 1, 1, kBlock, 1, 1, 0, stream, args,
                                   nullptr) != hipSuccess)
             return PERM_EHIP;
     }
     hipLaunchKernelGGL(finalize_residues, dim3(1), dim3(kBlock), 0, stream, partials, p.blocks,
-                       nprimes, residues_dev);
+                       nprimes, binary_primes(), residues_dev);
     return hipGetLastError() == hipSuccess ? PERM_OK : PERM_EHIP;
 }
 

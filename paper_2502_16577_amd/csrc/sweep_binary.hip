@@ -1,48 +1,59 @@
 // Exact permanent of a 0/1 matrix: the Gray-code Ryser / Nijenhuis-Wilf
 // sweep on y = 2x (integral: y_i = 2 a_{i,n-1} - r_i, each flip adds +-2 to
-// the rows of column j), reduced modulo several primes p_k = 2^61 - c_k.
+// the rows of column j), reduced modulo several primes p_k just above 2^50.
 //
 // Per step every lane forms the exact product of its y_i in FP64: rows are
-// grouped so that a group's product is below 2^53 for any |y_i| <= n, so each
-// group product is an exact integer and the term is zero exactly when one
-// group product is.  Terms that are zero are dropped (for random 0/1
-// matrices most are: about 91 % at n = 32, Bernoulli(1/2)).  Lanes with a
-// nonzero term append their group products to a per-wave queue in LDS; when
-// the queue holds 64 entries the whole wave drains it, one entry per lane,
-// doing the 61-bit modular products for every prime with all lanes busy.
-// Residues are reduced across lanes, blocks and the grid by modular addition
-// (exact, so the order does not matter).
+// grouped so that a group's product is at most 2^50 < p_k for any
+// |y_i| <= n, so each group product is an exact integer, already a residue,
+// and the term is zero exactly when one group product is.  Terms that are
+// zero are dropped (for random 0/1 matrices most are: about 91 % at n = 32,
+// Bernoulli(1/2)).  Lanes with a nonzero term append their group products to
+// a per-wave queue in LDS; when the queue holds 64 entries the whole wave
+// drains it, one entry per lane, multiplying the group products modulo every
+// prime with all lanes busy.  The modular products are FP64 operations
+// (mulmod50): residues are kept as signed integers in doubles.  Residues are
+// reduced across lanes, blocks and the grid by modular addition (exact, so
+// the order does not matter).
 #include "sweep_common.h"
 
 namespace perm {
 
-// Primes of the form 2^61 - c (2^61 - 1 is the Mersenne prime M61).
-__constant__ uint64_t kPrimeC[kMaxPrimes] = {1, 31, 45, 229, 259};
-
-__device__ __forceinline__ uint64_t prime_of(int k) { return (uint64_t(1) << 61) - kPrimeC[k]; }
-
-// x mod (2^61 - c) for x < 2^122, c < 2^9.
-__host__ __device__ __forceinline__ uint64_t reduce61(unsigned __int128 x, uint64_t c, uint64_t p)
+// a * b mod p as a signed residue of magnitude <= 0.875 p, for integers
+// |a|, |b| <= p held in doubles, p in (2^50, 2^50 + 2^40), pinv = fl(1/p).
+// a b = h + l exactly (error-free product); q = rint(h pinv) is within 0.875
+// of a b / p (three roundings of relative size 2^-53 on a quotient below
+// 2^50, plus the rounding to an integer); q p = qh + ql exactly; every
+// difference below is an integer of magnitude < 2^52, hence exact, and
+// (h - qh) + (l - ql) = a b - q p.  Contraction is off so the compiler keeps
+// exactly these operations.
+__device__ __forceinline__ double mulmod50(double a, double b, double p, double pinv)
 {
-    const uint64_t m61 = (uint64_t(1) << 61) - 1;
-    const uint64_t lo = uint64_t(x) & m61;
-    const unsigned __int128 hi = x >> 61;            // < 2^61
-    const unsigned __int128 y = hi * c + lo;         // < 2^70
-    const uint64_t lo2 = uint64_t(y) & m61;
-    const uint64_t hi2 = uint64_t(y >> 61);          // < 2^9 + 1
-    uint64_t z = lo2 + hi2 * c;                      // < 2^61 + 2^18
-    if (z >= p) z -= p;
-    return z;
+#pragma clang fp contract(off)
+    const double h = a * b;
+    const double l = __builtin_fma(a, b, -h);
+    const double q = __builtin_rint(h * pinv);
+    const double qh = q * p;
+    const double ql = __builtin_fma(q, p, -qh);
+    return (h - qh) + (l - ql);
 }
 
-__host__ __device__ __forceinline__ uint64_t mulmod61(uint64_t a, uint64_t b, uint64_t c, uint64_t p)
+// (acc + t) mod p, signed, magnitude <= p / 2 + 1, for |acc|, |t| <= p.
+__device__ __forceinline__ double addmod50(double acc, double t, double p, double pinv)
 {
-    return reduce61((unsigned __int128)a * b, c, p);
+#pragma clang fp contract(off)
+    const double s = acc + t;  // integers below 2^52: exact
+    return __builtin_fma(-__builtin_rint(s * pinv), p, s);
 }
 
-__host__ __device__ __forceinline__ uint64_t addmod(uint64_t a, uint64_t b, uint64_t p)
+// A signed residue |v| < p as the representative in [0, p).
+__device__ __forceinline__ uint64_t residue_u64(double v, double p)
 {
-    const uint64_t s = a + b;  // a, b < p < 2^61: no overflow
+    return uint64_t(v < 0.0 ? v + p : v);
+}
+
+__device__ __forceinline__ uint64_t addmod(uint64_t a, uint64_t b, uint64_t p)
+{
+    const uint64_t s = a + b;  // a, b < p < 2^51: no overflow
     return s >= p ? s - p : s;
 }
 
@@ -51,7 +62,7 @@ template <int N>
 struct BinGroups {
     static constexpr int bits = (N <= 2) ? 1 : (N <= 4) ? 2 : (N <= 8) ? 3 : (N <= 16) ? 4
                                : (N <= 32) ? 5 : 6;
-    static constexpr int G = 53 / bits;                 // |group product| <= 2^53
+    static constexpr int G = 50 / bits;                 // |group product| <= 2^50 < p
     static constexpr int M = (N + G - 1) / G;           // number of groups
 };
 
@@ -79,7 +90,7 @@ __global__ __launch_bounds__(kBlock) void prep_binary(int n, const double *__res
 // so it is accumulated exactly in int64 and reduced once per prime.
 __global__ void serial_binary(int n, const double *__restrict__ ycol,
                               const double *__restrict__ yneg, const double *__restrict__ y0,
-                              int nprimes, uint64_t *__restrict__ partials)
+                              int nprimes, BinaryPrimes P, uint64_t *__restrict__ partials)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     double y[12];
@@ -100,7 +111,7 @@ __global__ void serial_binary(int n, const double *__restrict__ ycol,
         R += (g & 1u) ? -int64_t(p) : int64_t(p);
     }
     for (int k = 0; k < nprimes; ++k) {
-        const uint64_t pk = prime_of(k);
+        const uint64_t pk = uint64_t(P.p[k]);
         const int64_t m = R % int64_t(pk);
         partials[k] = m < 0 ? uint64_t(m + int64_t(pk)) : uint64_t(m);
     }
@@ -124,39 +135,22 @@ __device__ __forceinline__ void group_products(const double (&y)[N],
     }
 }
 
-// |v| < 2^53 exact integer in a double -> uint64.
-__device__ __forceinline__ uint64_t exact_u64(double v)
-{
-    const double hi = __builtin_trunc(v * 0x1p-32);
-    const double lo = __builtin_fma(-hi, 0x1p32, v);
-    return (uint64_t(uint32_t(hi)) << 32) | uint64_t(uint32_t(lo));
-}
-
+// One queue entry: the signed group products of one nonzero term, multiplied
+// modulo every prime into the lane's residues.
 template <int M>
 __device__ __forceinline__ void drain_entry(const double *__restrict__ q, int slot, int nprimes,
-                                            uint64_t (&acc)[kMaxPrimes])
+                                            const BinaryPrimes &P, double (&acc)[kMaxPrimes])
 {
-    bool neg = false;
-    uint64_t a[M];
+    double g[M];
 #pragma unroll
-    for (int m = 0; m < M; ++m) {
-        double v = q[m * kQueueCap + slot];
-        if (v < 0.0) {
-            neg = !neg;
-            v = -v;
-        }
-        a[m] = exact_u64(v);
-    }
+    for (int m = 0; m < M; ++m) g[m] = q[m * kQueueCap + slot];
 #pragma unroll
     for (int k = 0; k < kMaxPrimes; ++k) {
         if (k < nprimes) {
-            const uint64_t c = kPrimeC[k];
-            const uint64_t p = (uint64_t(1) << 61) - c;
-            uint64_t P = a[0];  // < 2^53 < p
+            double t = g[0];  // |g| <= 2^50 < p: already a residue
 #pragma unroll
-            for (int m = 1; m < M; ++m) P = mulmod61(P, a[m], c, p);
-            const uint64_t t = (neg && P) ? p - P : P;
-            acc[k] = addmod(acc[k], t, p);
+            for (int m = 1; m < M; ++m) t = mulmod50(t, g[m], P.p[k], P.pinv[k]);
+            acc[k] = addmod50(acc[k], t, P.p[k], P.pinv[k]);
         }
     }
 }
@@ -172,6 +166,7 @@ __global__ __launch_bounds__(kBlock) void sweep_binary(const double *__restrict_
                                                        const double *__restrict__ yneg,
                                                        const double *__restrict__ y0, int c,
                                                        int nprimes, int skip_b, int nfrozen,
+                                                       const BinaryPrimes P,
                                                        uint64_t *__restrict__ partials)
 {
     constexpr int M = BinGroups<N>::M;
@@ -209,9 +204,9 @@ __global__ __launch_bounds__(kBlock) void sweep_binary(const double *__restrict_
         }
     }
 
-    uint64_t acc[kMaxPrimes];
+    double acc[kMaxPrimes];  // signed residues, |acc| <= p / 2 + 1
 #pragma unroll
-    for (int k = 0; k < kMaxPrimes; ++k) acc[k] = 0;
+    for (int k = 0; k < kMaxPrimes; ++k) acc[k] = 0.0;
     uint32_t count = 0;  // wave-uniform queue length
 
     auto push_term = [&](bool negative) {
@@ -235,7 +230,7 @@ __global__ __launch_bounds__(kBlock) void sweep_binary(const double *__restrict_
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            drain_entry<M>(q, int(count - 64 + lane), nprimes, acc);
+            drain_entry<M>(q, int(count - 64 + lane), nprimes, P, acc);
             count -= 64;
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
@@ -281,14 +276,14 @@ __global__ __launch_bounds__(kBlock) void sweep_binary(const double *__restrict_
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    if (lane < count) drain_entry<M>(q, int(lane), nprimes, acc);
+    if (lane < count) drain_entry<M>(q, int(lane), nprimes, P, acc);
 
     // wave reduction by modular addition, then across the block
 #pragma unroll
     for (int k = 0; k < kMaxPrimes; ++k) {
         if (k < nprimes) {
-            const uint64_t p = prime_of(k);
-            uint64_t v = acc[k];
+            const uint64_t p = uint64_t(P.p[k]);
+            uint64_t v = residue_u64(acc[k], P.p[k]);
 #pragma unroll
             for (int off = 32; off >= 1; off >>= 1) {
                 const uint64_t o = __shfl_xor(v, off, 64);
@@ -300,7 +295,7 @@ __global__ __launch_bounds__(kBlock) void sweep_binary(const double *__restrict_
     __syncthreads();
     if (threadIdx.x < uint32_t(nprimes)) {
         const int k = int(threadIdx.x);
-        const uint64_t p = prime_of(k);
+        const uint64_t p = uint64_t(P.p[k]);
         uint64_t v = 0;
 #pragma unroll
         for (int w = 0; w < kWavesPerBlock; ++w) v = addmod(v, red[w][k], p);
@@ -310,11 +305,12 @@ __global__ __launch_bounds__(kBlock) void sweep_binary(const double *__restrict_
 
 __global__ __launch_bounds__(kBlock) void finalize_residues(const uint64_t *__restrict__ partials,
                                                             int64_t count, int nprimes,
+                                                            BinaryPrimes P,
                                                             uint64_t *__restrict__ out)
 {
     __shared__ uint64_t red[kBlock];
     for (int k = 0; k < nprimes; ++k) {
-        const uint64_t p = prime_of(k);
+        const uint64_t p = uint64_t(P.p[k]);
         uint64_t v = 0;
         for (int64_t b = threadIdx.x; b < count; b += kBlock) v = addmod(v, partials[b * nprimes + k], p);
         red[threadIdx.x] = v;
@@ -331,14 +327,14 @@ __global__ __launch_bounds__(kBlock) void finalize_residues(const uint64_t *__re
 template <int N>
 static void launch_bin_n(const SweepPlan &p, const double *ycol, const double *yneg,
                          const double *y0, int nprimes, int skip_b, int nfrozen,
-                         uint64_t *partials, hipStream_t stream)
+                         const BinaryPrimes &P, uint64_t *partials, hipStream_t stream)
 {
     hipLaunchKernelGGL(sweep_binary<N>, dim3(unsigned(p.blocks)), dim3(kBlock), 0, stream, ycol,
-                       yneg, y0, p.log2_chunk, nprimes, skip_b, nfrozen, partials);
+                       yneg, y0, p.log2_chunk, nprimes, skip_b, nfrozen, P, partials);
 }
 
 using BinLauncher = void (*)(const SweepPlan &, const double *, const double *, const double *,
-                             int, int, int, uint64_t *, hipStream_t);
+                             int, int, int, const BinaryPrimes &, uint64_t *, hipStream_t);
 
 template <int... Ns>
 struct BinTable {
@@ -358,8 +354,9 @@ using BinaryTable =
 int launch_binary_residues(int n, const double *dense01, int nprimes, int skip_b, int nfrozen,
                            uint64_t *residues_dev, char *ws, hipStream_t stream)
 {
-    const SweepPlan p = plan_sweep(n, 0);
+    const SweepPlan p = plan_binary(n);
     const BinaryWs L = binary_ws_layout(n, p.blocks);
+    const BinaryPrimes P = binary_primes();
     double *ycol = reinterpret_cast<double *>(ws + L.ycol);
     double *yneg = reinterpret_cast<double *>(ws + L.yneg);
     double *y0 = reinterpret_cast<double *>(ws + L.y0);
@@ -368,16 +365,16 @@ int launch_binary_residues(int n, const double *dense01, int nprimes, int skip_b
     int64_t nparts = 1;
     if (n <= 12) {
         hipLaunchKernelGGL(serial_binary, dim3(1), dim3(64), 0, stream, n, ycol, yneg, y0, nprimes,
-                           partials);
+                           P, partials);
     } else {
         BinLauncher f = BinaryTable::get(n);
         if (!f) return PERM_EUNSUPPORTED;
-        f(p, ycol, yneg, y0, nprimes, skip_b > p.log2_chunk ? 0 : skip_b, nfrozen, partials,
+        f(p, ycol, yneg, y0, nprimes, skip_b > p.log2_chunk ? 0 : skip_b, nfrozen, P, partials,
           stream);
         nparts = p.blocks;
     }
     hipLaunchKernelGGL(finalize_residues, dim3(1), dim3(kBlock), 0, stream, partials, nparts,
-                       nprimes, residues_dev);
+                       nprimes, P, residues_dev);
     return hipGetLastError() == hipSuccess ? PERM_OK : PERM_EHIP;
 }
 

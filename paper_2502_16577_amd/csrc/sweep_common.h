@@ -85,7 +85,7 @@ __global__ void prep_dense_c128(int n, const perm_c128 *__restrict__ A, int64_t 
 __global__ void prep_binary(int n, const double *__restrict__ dense01, double *__restrict__ ycol,
                             double *__restrict__ yneg, double *__restrict__ y0);
 __global__ void finalize_residues(const uint64_t *__restrict__ partials, int64_t count,
-                                  int nprimes, uint64_t *__restrict__ out);
+                                  int nprimes, BinaryPrimes P, uint64_t *__restrict__ out);
 
 // Sums `count` double-double partials (components interleaved: partial b of
 // component q is at p[b * comps + q]) in a fixed order with one block, and

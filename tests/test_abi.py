@@ -75,7 +75,7 @@ def test_binary_argument_errors():
     f = lib.perm_binary_exact
     assert f(-1, cp.ctypes.data, ri.ctypes.data, 2, 0, limbs.ctypes.data, None, None, FAKE, big, None) == N.PERM_EINVAL
     assert f(2, cp.ctypes.data, ri.ctypes.data, 2, 0, None, None, None, FAKE, big, None) == N.PERM_EINVAL
-    assert f(2, cp.ctypes.data, ri.ctypes.data, 2, 6, limbs.ctypes.data, None, None, FAKE, big, None) == N.PERM_EINVAL
+    assert f(2, cp.ctypes.data, ri.ctypes.data, 2, 7, limbs.ctypes.data, None, None, FAKE, big, None) == N.PERM_EINVAL
     bad_ptr = np.array([0, 2, 1], np.int32)      # not monotone / wrong end
     assert f(2, bad_ptr.ctypes.data, ri.ctypes.data, 2, 0, limbs.ctypes.data, None, None, FAKE, big, None) == N.PERM_EINVAL
     bad_rows = np.array([1, 0], np.int32)
@@ -94,7 +94,7 @@ def test_binary_argument_errors():
     assert f(n, cpj.ctypes.data, rij.ctypes.data, n * n, 1, limbs.ctypes.data, None, None, FAKE, big, None) == N.PERM_ERANGE
 
 
-def test_binary_primes_are_primes_below_2_61():
+def test_binary_primes_are_primes_above_2_50():
     def is_prime(m):
         d, s = m - 1, 0
         while d % 2 == 0:
@@ -112,9 +112,10 @@ def test_binary_primes_are_primes_below_2_61():
                 return False
         return True
     lib = N.lib()
-    ps = [lib.perm_binary_prime(k) for k in range(5)]
-    assert len(set(ps)) == 5 and all(2 ** 60 < p < 2 ** 61 and is_prime(p) for p in ps)
-    assert lib.perm_binary_prime(5) == 0
+    ps = [lib.perm_binary_prime(k) for k in range(6)]
+    # the FP64 modular products need 2^50 < p < 2^50 + 2^40
+    assert len(set(ps)) == 6 and all(2 ** 50 < p < 2 ** 50 + 2 ** 40 and is_prime(p) for p in ps)
+    assert lib.perm_binary_prime(6) == 0 and lib.perm_binary_prime(-1) == 0
 
 
 @pytest.mark.parametrize("name", ["perm_sparse_f64", "perm_sparse_f64_gen"])
