@@ -252,11 +252,27 @@ def bench_rows():
                       ("40x40 0/1, 6 per row (seed 16582)", a)):
         nb = a01.shape[0]
         api.perm_binary_exact(a01)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         t0 = time.perf_counter()
+        e0.record(st)
         val, res = api.perm_binary_exact(a01)
+        e1.record(st)
         dt = time.perf_counter() - t0
-        line({"row": "a9 binary exact", "workload": name, "seconds": dt, "perm": str(val),
-              "primes": len(res), "subset_steps_per_s": 2 ** (nb - 1) / dt})
+        torch.cuda.synchronize()
+        gpu_s = e0.elapsed_time(e1) * 1e-3  # staging copy + kernels, on the call's stream
+        rec = {"row": "a9 binary exact", "workload": name, "seconds": dt, "gpu_seconds": gpu_s,
+               "perm": str(val), "primes": len(res), "subset_steps_per_s": 2 ** (nb - 1) / dt}
+        if nb == 32:
+            # every subset-step of a dense pattern costs the n adds and n - 1
+            # multiplies of the exact FP64 products (plus the zero test), the
+            # same FP64 slot count as the real sweep; the modular products of
+            # the 9 % nonzero terms come on top
+            ops = 2 * nb * 2 ** (nb - 1)
+            rec["roofline"] = {"bound": "alu", "achieved": ops / gpu_s / 1e12,
+                               "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s",
+                               "frac": ops / gpu_s / 1e12 / PEAK_ALU_TFLOPS,
+                               "ops_per_subset_step": 2 * nb}
+        line(rec)
         # the same through the kernel generated for the pattern
         t0 = time.perf_counter()
         api.perm_binary_exact(a01, generated=True)

@@ -309,15 +309,19 @@ std::string binary_kernel_source(int n, int n_cold, const std::vector<std::vecto
     // push the current term if it is nonzero
     o << "    auto push = [&](bool negative) {\n        double gp[M];\n";
     for (int m = 0; m < M; ++m) o << "        gp[" << m << "] = " << grp[m] << ";\n";
-    o << "        bool nz = true;\n"
-         "#pragma unroll\n        for (int m = 0; m < M; ++m) nz = nz && (gp[m] != 0.0);\n"
+    // zero test by FP64 minima; every lane stores without a branch, lanes
+    // with a zero term past the new entries (slot <= count + 63 < QCAP)
+    o << "        double mn = __builtin_fabs(gp[0]);\n"
+         "#pragma unroll\n        for (int m = 1; m < M; ++m) mn = __builtin_fmin(mn, __builtin_fabs(gp[m]));\n"
+         "        const bool nz = mn != 0.0;\n"
          "        if (negative) gp[0] = -gp[0];\n"
          "        const u64 ballot = __ballot(nz);\n"
          "        if (ballot == 0) return;\n"
          "        const u32 before = __builtin_amdgcn_mbcnt_hi(u32(ballot >> 32), __builtin_amdgcn_mbcnt_lo(u32(ballot), 0u));\n"
-         "        if (nz) {\n            const u32 slot = count + before;\n"
-         "#pragma unroll\n            for (int m = 0; m < M; ++m) q[m * QCAP + slot] = gp[m];\n        }\n"
-         "        count += u32(__builtin_popcountll(ballot));\n"
+         "        const u32 pc = u32(__builtin_popcountll(ballot));\n"
+         "        const u32 slot = nz ? count + before : count + pc + (lane - before);\n"
+         "#pragma unroll\n        for (int m = 0; m < M; ++m) q[m * QCAP + slot] = gp[m];\n"
+         "        count += pc;\n"
          "        if (count >= 64) {\n            wave_sync();\n"
          "            drain(int(count - 64 + lane));\n            count -= 64;\n            wave_sync();\n"
          "        }\n    };\n";

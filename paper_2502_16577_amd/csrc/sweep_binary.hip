@@ -212,20 +212,26 @@ __global__ __launch_bounds__(kBlock) void sweep_binary(const double *__restrict_
     auto push_term = [&](bool negative) {
         double gp[M];
         group_products<N>(y, gp);
-        bool nz = true;
+        // the term is nonzero iff the smallest |group product| is (FP64
+        // minima: no lane-mask logic on the scalar unit)
+        double mn = __builtin_fabs(gp[0]);
 #pragma unroll
-        for (int m = 0; m < M; ++m) nz = nz && (gp[m] != 0.0);
+        for (int m = 1; m < M; ++m) mn = __builtin_fmin(mn, __builtin_fabs(gp[m]));
+        const bool nz = mn != 0.0;
         if (negative) gp[0] = -gp[0];
         const uint64_t ballot = __ballot(nz);
         if (ballot == 0) return;
         const uint32_t before = __builtin_amdgcn_mbcnt_hi(uint32_t(ballot >> 32),
                                                           __builtin_amdgcn_mbcnt_lo(uint32_t(ballot), 0u));
-        if (nz) {
-            const uint32_t slot = count + before;
+        const uint32_t pc = uint32_t(__builtin_popcountll(ballot));
+        // Every lane stores, without a branch: nonzero terms to the next
+        // free slots, the others past them (slot <= count + 63 < kQueueCap,
+        // as count < 64 here), where a later push overwrites them before a
+        // drain reads that far.
+        const uint32_t slot = nz ? count + before : count + pc + (lane - before);
 #pragma unroll
-            for (int m = 0; m < M; ++m) q[m * kQueueCap + slot] = gp[m];
-        }
-        count += uint32_t(__builtin_popcountll(ballot));
+        for (int m = 0; m < M; ++m) q[m * kQueueCap + slot] = gp[m];
+        count += pc;
         if (count >= 64) {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
