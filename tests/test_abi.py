@@ -94,6 +94,24 @@ def test_binary_argument_errors():
     assert f(n, cpj.ctypes.data, rij.ctypes.data, n * n, 1, limbs.ctypes.data, None, None, FAKE, big, None) == N.PERM_ERANGE
 
 
+@pytest.mark.parametrize("n,enough", [(40, 4), (57, 6), (63, 6)])
+def test_binary_prime_count_follows_the_bound(n, enough):
+    # J_n: the Bregman-Minc bound is n! itself; with 50 bits per prime,
+    # `enough - 1` primes are refused before any GPU work (40! ~ 2^159.2,
+    # 57! ~ 2^255.9, 63! ~ 2^279.3)
+    import math
+    import numpy as np
+    assert (enough - 1) * 50 < math.log2(math.factorial(n)) + 1 <= enough * 50
+    lib = N.lib()
+    limbs = np.zeros(5, np.uint64)
+    used = ctypes.c_int(0)
+    cp = np.arange(0, n * n + 1, n, dtype=np.int32)
+    ri = np.tile(np.arange(n, dtype=np.int32), n)
+    rc = lib.perm_binary_exact(n, cp.ctypes.data, ri.ctypes.data, n * n, enough - 1,
+                               limbs.ctypes.data, None, ctypes.byref(used), FAKE, 1 << 30, None)
+    assert rc == N.PERM_ERANGE
+
+
 def test_binary_primes_are_primes_above_2_50():
     def is_prime(m):
         d, s = m - 1, 0
