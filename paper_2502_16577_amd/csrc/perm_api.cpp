@@ -463,7 +463,9 @@ static int binary_exact(int n, const int32_t *col_ptr, const int32_t *row_idx, i
         }
         const double step_cost = 2.0 * n + 5.0;
         double best = step_cost;
-        for (int b = 1; b <= std::min(plan.log2_chunk, 10); ++b) {
+        // skipped blocks are whole blocks of the kernel's walk (2^U steps)
+        const int bmin = n >= 14 ? 4 : 3;
+        for (int b = bmin; b <= std::min(plan.log2_chunk, 10); ++b) {
             double alive = 1.0;  // P(a lane's block is not provably zero)
             for (int i = 0; i < n; ++i) {
                 bool frozen = true;

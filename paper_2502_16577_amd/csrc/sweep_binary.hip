@@ -119,6 +119,10 @@ __global__ void serial_binary(int n, const double *__restrict__ ycol,
 
 constexpr int kQueueCap = 128;  // entries per wave; at most 63 wait between drains
 
+// Steps per block of the walk: 2^U (requires c > U, as the plan gives).
+template <int N>
+constexpr int binary_unroll() { return N >= 14 ? 4 : 3; }
+
 template <int N>
 __device__ __forceinline__ void group_products(const double (&y)[N],
                                                double (&gp)[BinGroups<N>::M])
@@ -244,8 +248,15 @@ __global__ __launch_bounds__(kBlock) void sweep_binary(const double *__restrict_
         }
     };
 
+    // Blocks of 2^U steps as in the real sweep: only the block's first step
+    // flips a column chosen at run time; step l + m flips column ctz(m) with
+    // a sign fixed by m (by bit U of l for m = 2^(U-1)), read from a constant
+    // address.  Zero-block skipping works on aligned blocks of 2^skip_b >= 2^U
+    // steps, tested at block starts.
+    constexpr int U = binary_unroll<N>();
+    constexpr uint32_t B = 1u << U;
     const uint32_t bmask = skip_b > 0 ? (1u << skip_b) - 1u : 0u;
-    for (uint32_t l = 0; l < C; l += 2) {
+    for (uint32_t l = 0; l < C; l += B) {
         if (l != 0) {
             const int j = __builtin_ctz(l);
             const bool add = (gray_low(l, kb, c) >> j) & 1u;
@@ -265,18 +276,24 @@ __global__ __launch_bounds__(kBlock) void sweep_binary(const double *__restrict_
                 const double *a = (add ? ycol : yneg) + (skip_b - 1) * N;
 #pragma unroll
                 for (int i = 0; i < N; ++i) y[i] += a[i];
-                l += bmask - 1u;  // the loop adds 2: next step is the next block's start
+                l += bmask + 1u - B;  // the loop adds B: next step is the next block's start
                 continue;
             }
         }
-        push_term(false);  // (-1)^g = +1 for even l
-        {
-            const bool add0 = gray_low(l + 1, kb, c) & 1u;
-            const double *a = add0 ? ycol : yneg;
+        push_term(false);  // (-1)^g = (-1)^m, l even
+#pragma unroll
+        for (uint32_t m = 1; m < B; ++m) {
+            const int j = __builtin_ctz(m);
+            const bool neg = (j + 1 < U) ? ((m >> (j + 1)) & 1u) : ((l >> U) & 1u);
+            // a fresh opaque offset per step keeps the compiler from hoisting
+            // these constant-address column loads into long-lived SGPRs
+            uint32_t zero = 0;
+            asm volatile("" : "+s"(zero));
+            const double *a = (neg ? yneg : ycol) + j * N + zero;
 #pragma unroll
             for (int i = 0; i < N; ++i) y[i] += a[i];
+            push_term((m & 1u) != 0u);
         }
-        push_term(true);   // odd step
     }
     // drain what is left (fewer than 64 entries)
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
