@@ -340,26 +340,23 @@ std::string binary_kernel_source(int n, int n_cold, const std::vector<std::vecto
              "            if ((l >> 4) & 1u) { " << ycolumn_code(rows, 3, '-') << "} else { "
           << ycolumn_code(rows, 3, '+') << "}\n            continue;\n        }\n";
     }
-    // the 16 steps of the block as a loop with one push site (the push and
-    // its modular drain are long; sixteen inlined copies would not fit the
-    // instruction cache); the cold rows are not written inside the loop, so
-    // their group products are computed once per block
-    o << "        for (u32 m = 0; m < 16u; ++m) {\n"
-         "            switch (m) {\n";
-    for (int m = 1; m < 16; ++m) {
-        const int j = __builtin_ctz(unsigned(m));
-        o << "            case " << m << ": ";
-        if (j + 1 < kGenUnroll) {
-            const bool neg = (m >> (j + 1)) & 1;
-            o << ycolumn_code(rows, j, neg ? '-' : '+');
-        } else {
-            o << "if ((l >> 4) & 1u) { " << ycolumn_code(rows, j, '-') << "} else { "
-              << ycolumn_code(rows, j, '+') << "} ";
+    // the 16 steps of the block, unrolled: each flip is its list of +-2
+    // updates; the cold rows are not written inside the block, so their
+    // group products are common to the sixteen pushes
+    for (int m = 0; m < 16; ++m) {
+        if (m > 0) {
+            const int j = __builtin_ctz(unsigned(m));
+            if (j + 1 < kGenUnroll) {
+                const bool neg = (m >> (j + 1)) & 1;
+                o << "        " << ycolumn_code(rows, j, neg ? '-' : '+') << "\n";
+            } else {
+                o << "        if ((l >> 4) & 1u) { " << ycolumn_code(rows, j, '-') << "} else { "
+                  << ycolumn_code(rows, j, '+') << "}\n";
+            }
         }
-        o << "break;\n";
+        o << "        push(" << ((m & 1) ? "true" : "false") << ");\n";
     }
-    o << "            default: break;\n            }\n"
-         "            push((m & 1u) != 0u);\n        }\n    }\n";
+    o << "    }\n";
     // what is left in the queue, then the modular reductions
     o << "    wave_sync();\n    if (lane < count) drain(int(lane));\n"
          "#pragma unroll\n    for (int k = 0; k < 6; ++k) {\n"
