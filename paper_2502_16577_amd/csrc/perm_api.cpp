@@ -41,13 +41,13 @@ SweepPlan plan_sweep(int n, int /*steps_per_op_hint*/)
     return p;
 }
 
-SweepPlan plan_binary(int n)
+SweepPlan plan_sweep_fine(int n)
 {
     SweepPlan p = plan_sweep(n, 0);
     if (n <= 12) return p;
-    // 2^20 lanes (4096 waves, 16 per SIMD) instead of 2^18: a lane's work
-    // depends on how many of its terms are nonzero, and with more, shorter
-    // chunks the waves that finish early are replaced by new ones
+    // 2^20 lanes (16384 waves, 16 per SIMD) instead of 2^18: a lane's work
+    // depends on the data (nonzero terms, skipped blocks), and with more,
+    // shorter chunks the waves that finish early are replaced by new ones
     const int total = n - 1;
     const int cmin = std::min(6, total - 8);
     const int c = std::max(cmin, total - 20);
@@ -223,7 +223,7 @@ size_t perm_workspace_bytes(int kind, int n, int64_t m)
         return grad_ws_layout(n, kind == PERM_KIND_GRAD_C128 ? 2 : 1, p.waves).total;
     }
     case PERM_KIND_BINARY: {
-        const SweepPlan p = plan_binary(n);
+        const SweepPlan p = plan_sweep_fine(n);
         return binary_ws_layout(n, p.blocks).total;
     }
     default: return 0;
@@ -398,7 +398,7 @@ static int binary_exact(int n, const int32_t *col_ptr, const int32_t *row_idx, i
     if (np < needed && !empty_line) return PERM_ERANGE;
     if (out_nprimes) *out_nprimes = np;
     if (empty_line) return PERM_OK;  // an empty row or column: no perfect matching
-    const SweepPlan plan = plan_binary(n);
+    const SweepPlan plan = plan_sweep_fine(n);
     const BinaryWs L = binary_ws_layout(n, plan.blocks);
     const int w = check_ws(ws, ws_bytes, L.total);
     if (w != PERM_OK) return w;

@@ -34,8 +34,10 @@ struct SweepPlan {
 };
 
 SweepPlan plan_sweep(int n, int steps_per_op_hint);
-// The exact binary sweep's plan: the same walk with 4x more lanes (n > 12).
-SweepPlan plan_binary(int n);
+// The same walk with 4x more, shorter chunks (n > 12), for sweeps whose work
+// per lane depends on the data (the exact binary sweeps: nonzero terms and
+// skipped blocks): waves that finish early are replaced by new ones.
+SweepPlan plan_sweep_fine(int n);
 
 // Primes of the exact binary path: the six smallest primes above 2^50.  A
 // residue, and the product of two residues divided by p, fit the 53-bit

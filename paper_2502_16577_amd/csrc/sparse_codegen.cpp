@@ -508,7 +508,7 @@ int launch_binary_gen(int n, int n_cold, const std::vector<std::vector<int>> &ro
                                   "perm_binary_gen", m);
         if (rc != PERM_OK) return rc;
     }
-    const SweepPlan p = plan_binary(n);
+    const SweepPlan p = plan_sweep_fine(n);
     const BinaryWs L = binary_ws_layout(n, p.blocks);
     double *ycol = reinterpret_cast<double *>(ws + L.ycol);
     double *yneg = reinterpret_cast<double *>(ws + L.yneg);

@@ -377,7 +377,7 @@ using BinaryTable =
 int launch_binary_residues(int n, const double *dense01, int nprimes, int skip_b, int nfrozen,
                            uint64_t *residues_dev, char *ws, hipStream_t stream)
 {
-    const SweepPlan p = plan_binary(n);
+    const SweepPlan p = plan_sweep_fine(n);
     const BinaryWs L = binary_ws_layout(n, p.blocks);
     const BinaryPrimes P = binary_primes();
     double *ycol = reinterpret_cast<double *>(ws + L.ycol);
