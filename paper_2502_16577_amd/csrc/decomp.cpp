@@ -150,37 +150,76 @@ Mat transpose(const Mat &A)
     return T;
 }
 
-// Moves row r and the columns c1, c2 to the front: row 0 = (alpha, beta, c),
-// column 0 = (alpha; d), column 1 = (beta; e), as in Eq. (expand).
-Mat front(const Mat &A, int r, int c1, int c2)
+// The three reductions of Algorithm 4 on row r with nonzero columns c1 (and
+// c2): rows are ordered r first, then the others in order; columns c1, c2
+// first, then the others in order (the row and columns moved to the front,
+// row 0 = (alpha, beta, c), column 0 = (alpha; d), column 1 = (beta; e)).
+// Each builds its child directly from A, with one allocation.
+struct Front {
+    int n;
+    int rows[PERM_MAX_N];  // rows[0] = r
+    int cols[PERM_MAX_N];  // cols[0] = c1 (, cols[1] = c2)
+    Front(const Mat &A, int r, int c1, int c2) : n(A.n)
+    {
+        int k = 0;
+        rows[k++] = r;
+        for (int i = 0; i < n; ++i)
+            if (i != r) rows[k++] = i;
+        k = 0;
+        cols[k++] = c1;
+        if (c2 >= 0) cols[k++] = c2;
+        for (int j = 0; j < n; ++j)
+            if (j != c1 && j != c2) cols[k++] = j;
+    }
+};
+
+// The minor without row r and column c1 (d1compress).
+Mat minor_of(const Mat &A, const Front &F)
 {
     const int n = A.n;
-    std::vector<int> rows{r}, cols{c1};
-    if (c2 >= 0) cols.push_back(c2);
-    for (int i = 0; i < n; ++i)
-        if (i != r) rows.push_back(i);
-    for (int j = 0; j < n; ++j)
-        if (j != c1 && j != c2) cols.push_back(j);
-    Mat P;
-    P.n = n;
-    P.a.resize(A.a.size());
-    for (int i = 0; i < n; ++i)
-        for (int j = 0; j < n; ++j) P.at(i, j) = A.at(rows[i], cols[j]);
-    return P;
-}
-
-// [alpha e + beta d, B]: the (n-1) x (n-1) matrix of the second term.
-Mat merged(const Mat &P, double alpha, double beta)
-{
-    const int n = P.n;
     Mat M;
     M.n = n - 1;
     M.a.resize(size_t(n - 1) * (n - 1));
     for (int i = 1; i < n; ++i) {
-        M.at(i - 1, 0) = alpha * P.at(i, 1) + beta * P.at(i, 0);
-        for (int j = 2; j < n; ++j) M.at(i - 1, j - 1) = P.at(i, j);
+        const double *src = &A.a[size_t(F.rows[i]) * n];
+        double *dst = &M.a[size_t(i - 1) * (n - 1)];
+        for (int j = 1; j < n; ++j) dst[j - 1] = src[F.cols[j]];
     }
     return M;
+}
+
+// [alpha e + beta d, B]: the (n-1) x (n-1) matrix of the second term.
+Mat merged(const Mat &A, const Front &F, double alpha, double beta)
+{
+    const int n = A.n;
+    Mat M;
+    M.n = n - 1;
+    M.a.resize(size_t(n - 1) * (n - 1));
+    for (int i = 1; i < n; ++i) {
+        const double *src = &A.a[size_t(F.rows[i]) * n];
+        double *dst = &M.a[size_t(i - 1) * (n - 1)];
+        dst[0] = alpha * src[F.cols[1]] + beta * src[F.cols[0]];
+        for (int j = 2; j < n; ++j) dst[j - 1] = src[F.cols[j]];
+    }
+    return M;
+}
+
+// The first term of d34compress: the permuted matrix with alpha and beta
+// replaced by zeros, [0 0 c; d e B].
+Mat zeroed_front(const Mat &A, const Front &F)
+{
+    const int n = A.n;
+    Mat Z;
+    Z.n = n;
+    Z.a.resize(size_t(n) * n);
+    for (int i = 0; i < n; ++i) {
+        const double *src = &A.a[size_t(F.rows[i]) * n];
+        double *dst = &Z.a[size_t(i) * n];
+        for (int j = 0; j < n; ++j) dst[j] = src[F.cols[j]];
+    }
+    Z.a[0] = 0.0;
+    Z.a[1] = 0.0;
+    return Z;
 }
 
 struct Decomposer {
@@ -200,57 +239,57 @@ struct Decomposer {
             leaves.push_back(Leaf{w, one});
             return;
         }
-        // row or column with the fewest nonzeros (Algorithm 4, getMinimumNnz)
-        int best = A.n + 1, best_idx = 0;
-        bool best_is_col = false;
-        for (int i = 0; i < A.n; ++i) {
-            int cr = 0, cc = 0;
-            for (int j = 0; j < A.n; ++j) {
-                cr += A.at(i, j) != 0.0;
-                cc += A.at(j, i) != 0.0;
+        // row or column with the fewest nonzeros (Algorithm 4, getMinimumNnz):
+        // all counts in one row-major pass; rows before columns, lower index
+        // first among equal counts
+        const int n = A.n;
+        int cr[PERM_MAX_N] = {}, cc[PERM_MAX_N] = {};
+        for (int i = 0; i < n; ++i) {
+            const double *row = &A.a[size_t(i) * n];
+            for (int j = 0; j < n; ++j) {
+                const int nz = row[j] != 0.0;
+                cr[i] += nz;
+                cc[j] += nz;
             }
-            if (cr < best) { best = cr; best_idx = i; best_is_col = false; }
-            if (cc < best) { best = cc; best_idx = i; best_is_col = true; }
+        }
+        int best = n + 1, best_idx = 0;
+        bool best_is_col = false;
+        for (int i = 0; i < n; ++i) {
+            if (cr[i] < best) { best = cr[i]; best_idx = i; best_is_col = false; }
+            if (cc[i] < best) { best = cc[i]; best_idx = i; best_is_col = true; }
         }
         if (best == 0) return;  // an empty row or column: this term is 0
         // the two-way split of minNnz 3 or 4 doubles the work items; once the
         // budget is spent such matrices are solved as they are
-        if (best > 4 || A.n <= min_leaf || (best > 2 && split_budget <= 0)) {
+        if (best > 4 || n <= min_leaf || (best > 2 && split_budget <= 0)) {
             if (int64_t(leaves.size()) >= max_leaves) { overflow = true; return; }
-            leaves.push_back(Leaf{w, A});
+            leaves.push_back(Leaf{w, std::move(A)});
             return;
         }
         if (best_is_col) A = transpose(A);  // perm(A^T) = perm(A)
         const int r = best_idx;
         int c1 = -1, c2 = -1;
-        for (int j = 0; j < A.n; ++j)
+        for (int j = 0; j < n; ++j)
             if (A.at(r, j) != 0.0) {
                 if (c1 < 0) c1 = j;
                 else if (c2 < 0) c2 = j;
             }
         if (best == 1) {  // d1compress: perm = alpha * perm(minor)
-            Mat P = front(A, r, c1, -1);
-            const double alpha = P.at(0, 0);
-            Mat M;
-            M.n = A.n - 1;
-            M.a.resize(size_t(M.n) * M.n);
-            for (int i = 1; i < A.n; ++i)
-                for (int j = 1; j < A.n; ++j) M.at(i - 1, j - 1) = P.at(i, j);
-            rec(std::move(M), w * alpha, depth + 1);
+            const Front F(A, r, c1, -1);
+            const double alpha = A.at(r, c1);
+            rec(minor_of(A, F), w * alpha, depth + 1);
             return;
         }
-        Mat P = front(A, r, c1, c2);
-        const double alpha = P.at(0, 0), beta = P.at(0, 1);
+        const Front F(A, r, c1, c2);
+        const double alpha = A.at(r, c1), beta = A.at(r, c2);
         if (best == 2) {  // d2compress: c = 0, only the merged term survives
-            rec(merged(P, alpha, beta), w, depth + 1);
+            rec(merged(A, F, alpha, beta), w, depth + 1);
             return;
         }
         // d34compress: perm = perm([0 0 c; d e B]) + perm([alpha e + beta d, B])
         --split_budget;
-        Mat Z = P;
-        Z.at(0, 0) = 0.0;
-        Z.at(0, 1) = 0.0;
-        rec(merged(P, alpha, beta), w, depth + 1);
+        Mat Z = zeroed_front(A, F);
+        rec(merged(A, F, alpha, beta), w, depth + 1);
         rec(std::move(Z), w, depth + 1);
     }
 };
