@@ -18,8 +18,9 @@
  *     pointers: the library validates them and derives the launch plan from
  *     them before any GPU work, then stages them into the workspace.
  *   - ws is a DEVICE workspace of at least perm_workspace_bytes(kind, n, m)
- *     bytes, owned by the caller; the library never allocates device memory
- *     and keeps no pointer after a call returns.
+ *     bytes, owned by the caller; the library allocates no device memory for
+ *     data (the *_gen entry points load compiled code modules, which stay
+ *     loaded) and keeps no pointer to caller memory after a call returns.
  *   - stream is a hipStream_t passed as void* (NULL = the null stream).  All
  *     calls are asynchronous on that stream except perm_binary_exact, which
  *     synchronises it to finish the Chinese remaindering on the host, and
