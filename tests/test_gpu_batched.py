@@ -131,3 +131,32 @@ def test_full_config_4096(oracle):
         assert abs(g[m][i, j] - want) <= 1e-10 * scale
         fd = oracle.grad_fd(a, i, j)
         assert abs(g[m][i, j] - fd) <= 1e-6 * max(abs(fd), 1e-300) or abs(g[m][i, j] - fd) <= 1e-10 * scale
+
+
+def test_largest_orders(oracle):
+    # orders 28 and 32 run in the kernel of orders 25..32 (one wave per SIMD):
+    # k = 28, a Haar submatrix, against the oracle (permanent, one minor, and
+    # Laplace's identity on every row and column at the oracle's Ryser scale);
+    # k = 32 (2^31 subsets), U[0,1) entries, against the real forward and
+    # adjoint kernels and the same identity (no cancellation: relative gates)
+    a32 = W.uniform(32, 1700).astype(np.complex128)
+    a28 = mixed_batch([28], 61)[0]
+    mats = [a32, a28]
+    out, g, _, _ = run(mats, use_graph=False)
+    want, r = oracle.ryser(a28, with_abs=True)
+    assert abs(out[1] - want) <= 1e-13 * r, (out[1], want, r)
+    m28 = oracle.minor(a28, 4, 19)
+    assert abs(g[1][4, 19] - m28) <= 1e-10 * oracle.perm(np.abs(np.delete(np.delete(a28, 4, 0), 19, 1)))
+    for i in range(28):
+        assert abs(np.dot(a28[i], g[1][i]) - want) <= 1e-12 * r, i
+        assert abs(np.dot(a28[:, i], g[1][:, i]) - want) <= 1e-12 * r, i
+    ref = api.perm_dense_f64(torch.from_numpy(a32.real.copy()).to(DEV)).item()
+    assert abs(out[0] - ref) <= 1e-10 * ref, (out[0], ref)
+    # the single-matrix adjoint on the same input (its n = 32 minors are
+    # checked against the oracle in the gradient tests)
+    _, g1 = api.perm_grad(torch.from_numpy(a32.real.copy()).to(DEV))
+    g1 = g1.cpu().numpy()
+    assert np.all(np.abs(g[0] - g1) <= 1e-10 * np.abs(g1))
+    for i in range(32):
+        assert abs(np.dot(a32[i], g[0][i]) - out[0]) <= 1e-10 * abs(out[0]), i
+        assert abs(np.dot(a32[:, i], g[0][:, i]) - out[0]) <= 1e-10 * abs(out[0]), i

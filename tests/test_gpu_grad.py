@@ -9,6 +9,9 @@ identity sum_j a_ij G_ij = perm(A) is checked on every row and column.
 Finite differences: max |G - FD| <= 1e-6 * max |FD| (FD from the oracle,
 exact for an affine map up to rounding).
 """
+import json
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -98,3 +101,32 @@ def test_autograd_backward_value():
     (3.0 * p).backward()
     _, g = api.perm_grad(A.detach())
     assert torch.allclose(A.grad, 3.0 * g, rtol=0, atol=0)
+
+
+def test_largest_order_real(oracle):
+    # n = 32, the largest order perm_grad takes (2^31 subsets), on the 32 x 32
+    # U[0,1) input whose permanent the oracle value in tests/golden holds: the
+    # permanent against it, one sampled minor from the oracle (a 31 x 31 sweep
+    # on the host), and Laplace's identity on every row and column, which ties
+    # all n^2 entries to the permanent
+    with open(os.path.join(os.path.dirname(__file__), "golden", "full_size.json")) as f:
+        gold = json.load(f)["u32"]
+    n = 32
+    a = W.uniform(n, W.SEED_U32)
+    assert W.digest(a) == gold["digest"]
+    want = gold["value"][0] + gold["value"][1]
+    p, g = gpu_grad(a)
+    assert abs(p - want) <= 1e-10 * want, (p, want)
+    i, j = 5, 27
+    m = oracle.minor(a, i, j)
+    assert abs(g[i, j] - m) <= 1e-10 * m, (g[i, j], m)
+    for k in range(n):
+        assert abs(np.dot(a[k], g[k]) - want) <= 1e-10 * want, k
+        assert abs(np.dot(a[:, k], g[:, k]) - want) <= 1e-10 * want, k
+
+
+def test_empty_matrix():
+    # perm of the 0 x 0 matrix is 1; its gradient has no entries
+    for dtype in (torch.float64, torch.complex128):
+        p, g = api.perm_grad(torch.zeros((0, 0), dtype=dtype, device=DEV))
+        assert p.item() == 1 and g.shape == (0, 0)
