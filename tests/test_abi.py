@@ -188,3 +188,16 @@ def test_dense_ex_option_errors():
     assert lib.perm_dense_f64_ex(20, FAKE, 20, ctypes.byref(bad), FAKE, FAKE, big, None) == N.PERM_EINVAL
     ok = PermOptions(1, 4, 1 << 20, 12)
     assert lib.perm_dense_f64_ex(20, FAKE, 20, ctypes.byref(ok), FAKE, None, 0, None) == N.PERM_EWORKSPACE
+
+
+def test_binary_empty_matrix_on_the_host():
+    # n = 0: permanent 1 (the empty product), decided before any GPU work
+    import numpy as np
+    lib = N.lib()
+    limbs = np.zeros(5, np.uint64)
+    res = np.zeros(6, np.uint64)
+    used = ctypes.c_int(0)
+    cp = np.zeros(1, np.int32)
+    assert lib.perm_binary_exact(0, cp.ctypes.data, None, 0, 0, limbs.ctypes.data, res.ctypes.data,
+                                 ctypes.byref(used), None, 0, None) == N.PERM_OK
+    assert list(limbs) == [1, 0, 0, 0, 0] and used.value == 3 and list(res[:3]) == [1, 1, 1]

@@ -162,3 +162,30 @@ def test_all_equal_paper_size(n):
         A = torch.from_numpy(a).to(DEV)
         got = api.perm_dense_f64_ex(A, max_steps_per_launch=1 << 32).item()
         assert abs(got - exact) <= 1e-10 * exact, (n, got, exact, abs(got - exact) / exact)
+
+
+def test_empty_and_degenerate_inputs():
+    # n = 0: the empty product
+    z = torch.zeros((0, 0), dtype=torch.complex128, device=DEV)
+    assert complex(api.perm(z).cpu().item()) == 1.0
+    assert api.perm(torch.zeros((0, 0), dtype=torch.float64, device=DEV)).item() == 1.0
+    assert api.perm_sparse_f64(0, np.zeros(1, np.int32), np.zeros(0, np.int32), np.zeros(0)).item() == 1.0
+    # a zero row keeps x_i = 0 through the whole walk: every term is an exact zero
+    for n in (13, 20, 27):
+        a = W.uniform(n, 900 + n)
+        a[n // 2, :] = 0.0
+        assert gpu_perm(a) == 0.0
+        c = W.haar_block(2 * n, n, 950 + n)
+        c[n // 3, :] = 0.0
+        assert complex(api.perm(torch.from_numpy(c).to(DEV)).cpu().item()) == 0.0
+    # a sparse matrix with an empty row, staged and generated paths
+    for n in (10, 16):
+        a = W.sparse_rows(n, 3, 970 + n) * np.random.default_rng(n).random((n, n))
+        a[2, :] = 0.0
+        cp, ri, va = [0], [], []
+        for j in range(n):
+            nz = np.nonzero(a[:, j])[0]
+            ri += list(nz); va += list(a[nz, j]); cp.append(len(ri))
+        cp, ri, va = np.array(cp, np.int32), np.array(ri, np.int32), np.array(va)
+        assert api.perm_sparse_f64(n, cp, ri, va).item() == 0.0
+        assert api.perm_sparse_f64_gen(n, cp, ri, va).item() == 0.0
