@@ -137,7 +137,8 @@ int perm_dense_c128(int n, const perm_c128 *A, int64_t lda, perm_c128 *out,
  * product runs over all n rows).  The pattern is validated on the host and
  * staged into the workspace as column copies; the call returns once the
  * staging copy has completed (it synchronises `stream`), and the sweep then
- * runs asynchronously.
+ * runs asynchronously.  A row or column without a nonzero value gives
+ * exactly 0 (written by a one-thread kernel; no sweep, no synchronisation).
  *   col_ptr  host int32[n+1], col_ptr[0] = 0, nondecreasing, col_ptr[n] = nnz
  *   row_idx  host int32[nnz], strictly increasing within a column, in [0, n)
  *   vals     host double[nnz]

@@ -276,6 +276,26 @@ int perm_dense_c128(int n, const perm_c128 *A, int64_t lda, perm_c128 *out, void
                              static_cast<hipStream_t>(stream));
 }
 
+// A row or column without a nonzero value meets every permutation, so the
+// permanent is exactly 0 (the sweep's terms would cancel only to rounding).
+static bool has_empty_line(int n, const int32_t *col_ptr, const int32_t *row_idx,
+                           const double *vals)
+{
+    std::vector<char> row_hit(n, 0);
+    for (int j = 0; j < n; ++j) {
+        bool col_hit = false;
+        for (int32_t q = col_ptr[j]; q < col_ptr[j + 1]; ++q)
+            if (vals[q] != 0.0) {
+                col_hit = true;
+                row_hit[row_idx[q]] = 1;
+            }
+        if (!col_hit) return true;
+    }
+    for (int i = 0; i < n; ++i)
+        if (!row_hit[i]) return true;
+    return false;
+}
+
 int perm_sparse_f64(int n, const int32_t *col_ptr, const int32_t *row_idx, const double *vals,
                     int32_t nnz, double *out, void *ws, size_t ws_bytes, void *stream)
 {
@@ -286,6 +306,7 @@ int perm_sparse_f64(int n, const int32_t *col_ptr, const int32_t *row_idx, const
     hipStream_t st = static_cast<hipStream_t>(stream);
     char *base = static_cast<char *>(ws);
     if (n == 0) return launch_dense_f64(0, nullptr, 0, out, base, st);
+    if (has_empty_line(n, col_ptr, row_idx, vals)) return launch_write_f64(0.0, out, st);
     // Stage the matrix row-major behind the dense workspace; the sweep then
     // updates x with whole columns held in scalar registers (zeros included).
     const size_t off = perm_workspace_bytes(PERM_KIND_DENSE_F64, n, 0);
@@ -311,6 +332,7 @@ int perm_sparse_f64_gen(int n, const int32_t *col_ptr, const int32_t *row_idx,
     if (n < kSparseGenMinN)  // a few thousand steps: the staged-column sweep
         return perm_sparse_f64(n, col_ptr, row_idx, vals, nnz, out, ws, ws_bytes, stream);
     hipStream_t st = static_cast<hipStream_t>(stream);
+    if (has_empty_line(n, col_ptr, row_idx, vals)) return launch_write_f64(0.0, out, st);
     char *base = static_cast<char *>(ws);
     // Columns by ascending count (the permanent is invariant under column
     // permutations): the low columns, flipped at 15 of every 16 steps, then

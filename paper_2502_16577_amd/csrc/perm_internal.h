@@ -197,6 +197,8 @@ int launch_binary_gen(int n, int n_cold, const std::vector<std::vector<int>> &ro
                       hipStream_t stream);
 std::string binary_gen_source(int n, int n_cold, const std::vector<std::vector<int>> &rows);
 
+// out[0] = v (a kernel, so it can sit in a captured graph).
+int launch_write_f64(double v, double *out, hipStream_t stream);
 int launch_dense_f64(int n, const double *A, int64_t lda, double *out, char *ws,
                      hipStream_t stream);
 int launch_dense_f64_opt(int n, const double *A, int64_t lda, double *out, const SweepOptions &o,

@@ -18,4 +18,12 @@ __global__ __launch_bounds__(kBlock) void finalize_partials(const dd *__restrict
     }
 }
 
+__global__ void write_f64(double v, double *__restrict__ out) { out[0] = v; }
+
+int launch_write_f64(double v, double *out, hipStream_t stream)
+{
+    hipLaunchKernelGGL(write_f64, dim3(1), dim3(1), 0, stream, v, out);
+    return hipGetLastError() == hipSuccess ? PERM_OK : PERM_EHIP;
+}
+
 }  // namespace perm

@@ -178,14 +178,22 @@ def test_empty_and_degenerate_inputs():
         c = W.haar_block(2 * n, n, 950 + n)
         c[n // 3, :] = 0.0
         assert complex(api.perm(torch.from_numpy(c).to(DEV)).cpu().item()) == 0.0
-    # a sparse matrix with an empty row, staged and generated paths
+    # sparse matrices with an empty row, an empty column, or a stored zero as
+    # a column's only entry: exactly 0 on the staged and generated paths
     for n in (10, 16):
-        a = W.sparse_rows(n, 3, 970 + n) * np.random.default_rng(n).random((n, n))
-        a[2, :] = 0.0
-        cp, ri, va = [0], [], []
-        for j in range(n):
-            nz = np.nonzero(a[:, j])[0]
-            ri += list(nz); va += list(a[nz, j]); cp.append(len(ri))
-        cp, ri, va = np.array(cp, np.int32), np.array(ri, np.int32), np.array(va)
-        assert api.perm_sparse_f64(n, cp, ri, va).item() == 0.0
-        assert api.perm_sparse_f64_gen(n, cp, ri, va).item() == 0.0
+        for case in ("row", "col", "stored zero"):
+            a = W.sparse_rows(n, 3, 970 + n) * (0.5 + np.random.default_rng(n).random((n, n)))
+            if case == "row":
+                a[2, :] = 0.0
+            else:
+                a[:, 2] = 0.0
+            cp, ri, va = [0], [], []
+            for j in range(n):
+                nz = list(np.nonzero(a[:, j])[0])
+                vals = list(a[nz, j])
+                if case == "stored zero" and j == 2:
+                    nz, vals = [4], [0.0]
+                ri += nz; va += vals; cp.append(len(ri))
+            cp, ri, va = np.array(cp, np.int32), np.array(ri, np.int32), np.array(va)
+            assert api.perm_sparse_f64(n, cp, ri, va).item() == 0.0, (n, case)
+            assert api.perm_sparse_f64_gen(n, cp, ri, va).item() == 0.0, (n, case)
