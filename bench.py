@@ -65,9 +65,18 @@ def cpu_baseline(a, target_seconds=12.0):
     orc.ryser_sample(a, 1024, nch, threads)
     dt = time.perf_counter() - t0
     steps = nch * chunk
+    # the same oracle on one thread, over a smaller sample (about 2 s)
+    total = (1 << (N - 1)) // chunk
+    n1 = min(max(1, int(nch * 2.0 / (max(dt, 1e-3) * threads))), total)
+    t0 = time.perf_counter()
+    orc.ryser_sample(a, 0, n1, 1)
+    dt1 = time.perf_counter() - t0
     return {"value": steps / dt, "unit": "subset-steps/s", "cores": threads, "kind": "oracle",
             "sample": f"{steps} of the 2^31 Gray steps of the same 32x32 U[0,1) matrix "
-                      f"({nch} chunks of {chunk} steps, long double), {dt:.2f} s wall"}
+                      f"({nch} chunks of {chunk} steps, long double), {dt:.2f} s wall",
+            "single_thread": {"value": n1 * chunk / dt1, "unit": "subset-steps/s",
+                              "sample": f"{n1} chunks of {chunk} steps on one thread, "
+                                        f"{dt1:.2f} s wall"}}
 
 
 def bench_batched(reps: int = 5, use_graph: bool = True, baselines: bool = True):
