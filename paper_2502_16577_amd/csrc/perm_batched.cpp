@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <iterator>
 #include <cstring>
 #include <vector>
 
@@ -183,13 +184,11 @@ int perm_batched_plan_create(int count, const int32_t *k, const int64_t *offset,
     P->want_grad = want_grad ? 1 : 0;
     P->k.assign(k, k + count);
     P->off.assign(offset, offset + count);
-    // the workspace must hold the largest layout over every tuning candidate
-    size_t mx = 0;
-    for (int ct : kTuneChunks) {
-        P->tune.log2_chunk = ct;
-        derive(*P);
-        mx = std::max(mx, P->total);
-    }
+    // the workspace must hold the largest layout over every tuning candidate:
+    // the shortest chunks give every matrix the most items, so that one
+    P->tune.log2_chunk = *std::min_element(std::begin(kTuneChunks), std::end(kTuneChunks));
+    derive(*P);
+    const size_t mx = P->total;
     P->tune = BatchTuning{};
     derive(*P);
     P->ws_max = std::max(mx, P->total);
