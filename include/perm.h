@@ -27,6 +27,10 @@
  *     perm_sparse_f64, which synchronises it once its host pattern is staged.
  *   - Results are deterministic for fixed inputs and sizes: partial sums are
  *     combined in a fixed order and no result goes through atomics.
+ *   - perm_dense_f64(_ex), perm_dense_c128, perm_grad and perm_weighted_sum
+ *     only enqueue kernels (no allocation, copy, memset or synchronisation),
+ *     so they can be captured into a hipGraph; the sparse and binary entry
+ *     points stage host data and synchronise, so they cannot.
  *   - n == 0 yields 1 (the empty product); n < 0 or n > PERM_MAX_N is
  *     PERM_EINVAL.  Errors are reported as negative return values before any
  *     GPU work is queued, except PERM_EHIP which reports a HIP runtime error.

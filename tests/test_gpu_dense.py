@@ -197,3 +197,36 @@ def test_empty_and_degenerate_inputs():
             cp, ri, va = np.array(cp, np.int32), np.array(ri, np.int32), np.array(va)
             assert api.perm_sparse_f64(n, cp, ri, va).item() == 0.0, (n, case)
             assert api.perm_sparse_f64_gen(n, cp, ri, va).item() == 0.0, (n, case)
+
+
+def test_graph_capture_replays():
+    # the dense sweeps are kernel launches only (no allocation, copy or
+    # memset), so they can be captured into a graph: each replay, with new
+    # inputs copied in eagerly between replays, equals the eager call bit for bit
+    ar = [torch.from_numpy(W.uniform(24, 40 + s)).to(DEV) for s in range(3)]
+    ac = [torch.from_numpy(W.haar_block(48, 20, 50 + s)).to(DEV) for s in range(3)]
+    A = ar[0].clone()
+    C = ac[0].clone()
+    out_r = torch.empty((), dtype=torch.float64, device=DEV)
+    out_c = torch.empty((), dtype=torch.complex128, device=DEV)
+    ws_r = torch.empty(api.workspace_bytes(1, 24), dtype=torch.uint8, device=DEV)
+    ws_c = torch.empty(api.workspace_bytes(2, 20), dtype=torch.uint8, device=DEV)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):  # warm-up outside the capture
+        api.perm_dense_f64(A, out=out_r, ws=ws_r)
+        api.perm_dense_c128(C, out=out_c, ws=ws_c)
+    torch.cuda.current_stream().wait_stream(s)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        api.perm_dense_f64(A, out=out_r, ws=ws_r)
+        api.perm_dense_c128(C, out=out_c, ws=ws_c)
+    for rep in range(3):
+        A.copy_(ar[rep])
+        C.copy_(ac[rep])
+        g.replay()
+        torch.cuda.synchronize()
+        got_r, got_c = out_r.item(), complex(out_c.cpu().item())
+        want_r = api.perm_dense_f64(ar[rep]).item()
+        want_c = complex(api.perm_dense_c128(ac[rep]).cpu().item())
+        assert got_r == want_r and got_c == want_c, rep
