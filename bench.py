@@ -53,7 +53,8 @@ def traffic_bytes():
 def cpu_baseline(a, target_seconds=12.0):
     from oracle.oracle import default
     orc = default()
-    threads = os.cpu_count() or 1
+    # the host's share of cores: OMP_NUM_THREADS where set, at most 16
+    threads = min(int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1), 16)
     chunk = orc.CHUNK_STEPS
     nch = 256
     t0 = time.perf_counter()
