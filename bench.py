@@ -309,9 +309,19 @@ def bench_rows():
         cplx = dtype == "c128"
         # G = sum over subsets of V tau^T: n^2 multiply-adds per subset (x2 for complex V)
         gemm = (4 if cplx else 2) * n * n * 2 ** (n - 1)
+        # FP64 slot operations per subset-step of the sweep as designed: the x
+        # update, the forward product, three products per row for the
+        # leave-one-out products (prefix, combine, suffix), the window sums of
+        # V, and the 16-lane partial sums of V for the low columns (16 adds
+        # per component in each of the two waves); a complex product is 4
+        ops = (20 * n + 60) if cplx else (6 * n + 31)
+        achieved = ops * 2 ** (n - 1) / (ms * 1e-3) / 1e12
         line({"row": "a10 perm + dperm/dA", "workload": f"24x24 {dtype}", "ms": ms,
               "subset_steps_per_s": 2 ** (n - 1) / (ms * 1e-3),
-              "gemm_equivalent_tflops": gemm / (ms * 1e-3) / 1e12})
+              "gemm_equivalent_tflops": gemm / (ms * 1e-3) / 1e12,
+              "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_ALU_TFLOPS,
+                           "unit": "TFLOP/s", "frac": achieved / PEAK_ALU_TFLOPS,
+                           "ops_per_subset_step": ops}})
 
 
 # Best published GPU kernel (x_reg-A_shr-rebuild with CEG, Quadro GV100) of
