@@ -153,6 +153,10 @@ def bench_batched(reps: int = 5, use_graph: bool = True, baselines: bool = True)
     # GEMM-equivalent work of the contraction G += V tau^T: 2 real GEMMs (Re, Im
     # of V) x 2 k^2 flops per subset; the windowed kernel issues 1/16 of it on MFMA
     mfma_flops = float(sum((2 ** (int(k) - 1)) * 4 * int(k) ** 2 for k in ks))
+    # FP64 slot operations of the complex sweep with its gradient, 20k + 60
+    # per subset-step (as for the single-matrix adjoint)
+    alu_ops = float(sum((2 ** (int(k) - 1)) * (20 * int(k) + 60) for k in ks))
+    alu_tflops = alu_ops / (batch_ms * 1e-3) / 1e12
     return {
         "workload": "4096 complex128 k x k submatrices, k ~ U{8..24}, rows/cols drawn with "
                     "repetition from a 64x64 Haar unitary (seeds 16583, 16584); perm + dperm/dA",
@@ -169,6 +173,9 @@ def bench_batched(reps: int = 5, use_graph: bool = True, baselines: bool = True)
         "speedup_vs_plain_solver": plain_ms / batch_ms,
         "speedup_vs_per_matrix_perm_grad": per_grad_ms / batch_ms,
         "gemm_equivalent_tflops": mfma_flops / (batch_ms * 1e-3) / 1e12,
+        "roofline": {"bound": "alu", "achieved": alu_tflops, "peak": PEAK_ALU_TFLOPS,
+                     "unit": "TFLOP/s", "frac": alu_tflops / PEAK_ALU_TFLOPS,
+                     "ops_per_subset_step": "20k + 60"},
     }
 
 
