@@ -230,3 +230,20 @@ def test_graph_capture_replays():
         want_r = api.perm_dense_f64(ar[rep]).item()
         want_c = complex(api.perm_dense_c128(ac[rep]).cpu().item())
         assert got_r == want_r and got_c == want_c, rep
+
+
+@pytest.mark.parametrize("n", [13, 14, 15, 17])
+def test_options_at_small_orders(oracle, n):
+    # the smallest orders of the block sweep (8-step blocks at n = 13, 16-step
+    # blocks from n = 14): every lane count and re-seed interval, clamped by
+    # the library to valid chunks, gives the oracle's value
+    a = W.uniform(n, 1900 + n)
+    A = torch.from_numpy(a).to(DEV)
+    want = oracle.ryser(a)
+    for ll in (0, 8, 10, 12, 18):
+        for r in (0, 1, 3, 4, 9):
+            for acc in (api.ACC_TWOSUM, api.ACC_PLAIN, api.ACC_KAHAN):
+                v = api.perm_dense_f64_ex(A, accumulation=acc, log2_reseed=r, log2_lanes=ll).item()
+                assert abs(v - want) <= 1e-10 * abs(want), (ll, r, acc, v, want)
+    v = api.perm_dense_f64_ex(A, max_steps_per_launch=1 << 8).item()
+    assert abs(v - want) <= 1e-10 * abs(want)
