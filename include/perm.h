@@ -118,12 +118,25 @@ typedef struct {
                                       to [2^8, 2^18] (or the default if larger), to chunks
                                       longer than the 16-step block, and to chunks of at
                                       most 2^31 steps */
+    int64_t first_launch;          /* the first launch of the split sweep to run */
+    int64_t launch_count;          /* how many to run; 0 = through the last (see
+                                      perm_dense_f64_ex) */
 } perm_options;
 
 /* perm_dense_f64 with options (opt may be NULL).  PERM_EINVAL for an unknown
- * accumulation mode or negative fields. */
+ * accumulation mode, negative fields, or first_launch at or beyond the number
+ * of launches.  A long sweep can be run as several calls, each over a range
+ * of its launches (perm_dense_f64_launches gives their number), in order,
+ * with the same A, options (apart from the range), workspace and stream: a
+ * call adds its launches' block sums to the partials the earlier calls left
+ * in the workspace and writes the running total to out, so out holds the
+ * permanent after the call that runs the last launch. */
 int perm_dense_f64_ex(int n, const double *A, int64_t lda, const perm_options *opt,
                       double *out, void *ws, size_t ws_bytes, void *stream);
+
+/* Number of launches perm_dense_f64_ex splits the sweep of order n into under
+ * these options (opt may be NULL); negative (PERM_EINVAL) for invalid options. */
+int64_t perm_dense_f64_launches(int n, const perm_options *opt);
 
 /*
  * Permanent of a dense complex n x n matrix: the same sweep with complex x

@@ -41,6 +41,7 @@ SIGNATURES = [
     ("perm_workspace_bytes", _sz, [_int, _int, _i64]),
     ("perm_dense_f64", _int, [_int, _vp, _i64, _vp, _vp, _sz, _vp]),
     ("perm_dense_f64_ex", _int, [_int, _vp, _i64, _vp, _vp, _vp, _sz, _vp]),
+    ("perm_dense_f64_launches", _i64, [_int, _vp]),
     ("perm_dense_c128", _int, [_int, _vp, _i64, _vp, _vp, _sz, _vp]),
     ("perm_sparse_f64", _int, [_int, _vp, _vp, _vp, _i32, _vp, _vp, _sz, _vp]),
     ("perm_sparse_f64_gen", _int, [_int, _vp, _vp, _vp, _i32, _vp, _vp, _sz, _vp]),

@@ -59,7 +59,8 @@ def perm_dense_f64(A: torch.Tensor, out: torch.Tensor | None = None, ws=None) ->
 class PermOptions(ctypes.Structure):
     """perm_options of include/perm.h."""
     _fields_ = [("accumulation", ctypes.c_int), ("log2_reseed", ctypes.c_int),
-                ("max_steps_per_launch", ctypes.c_int64), ("log2_lanes", ctypes.c_int)]
+                ("max_steps_per_launch", ctypes.c_int64), ("log2_lanes", ctypes.c_int),
+                ("first_launch", ctypes.c_int64), ("launch_count", ctypes.c_int64)]
 
 
 ACC_TWOSUM = 0
@@ -69,11 +70,15 @@ ACC_KAHAN = 2
 
 def perm_dense_f64_ex(A: torch.Tensor, accumulation: int = ACC_TWOSUM, log2_reseed: int = 0,
                       max_steps_per_launch: int = 0, log2_lanes: int = 0,
+                      first_launch: int = 0, launch_count: int = 0,
                       out: torch.Tensor | None = None, ws=None):
     """perm_dense_f64 with options: accumulation ACC_TWOSUM (default) or
     ACC_PLAIN (the paper's plain-double "DD" variant), the exact re-seed
     interval 2^log2_reseed (0 = default) and the longest single launch.
-    ACC_KAHAN selects Kahan-compensated lane sums (the paper's "Kahan")."""
+    ACC_KAHAN selects Kahan-compensated lane sums (the paper's "Kahan").
+    first_launch / launch_count run part of a split sweep: calls over
+    consecutive ranges of its launches (dense_f64_launches), in order and with
+    the same ws, leave the permanent in out after the last one."""
     _check_square(A)
     if A.dtype != torch.float64:
         raise TypeError("float64 expected")
@@ -81,12 +86,22 @@ def perm_dense_f64_ex(A: torch.Tensor, accumulation: int = ACC_TWOSUM, log2_rese
     if out is None:
         out = torch.empty((), dtype=torch.float64, device=A.device)
     ws, need = _workspace(N.KIND_DENSE_F64, n, 0, A.device, ws)
-    opt = PermOptions(accumulation, log2_reseed, max_steps_per_launch, log2_lanes)
+    opt = PermOptions(accumulation, log2_reseed, max_steps_per_launch, log2_lanes, first_launch,
+                      launch_count)
     st = N.lib().perm_dense_f64_ex(n, A.data_ptr() if n else None, A.stride(0) if n else 0,
                                    ctypes.byref(opt), out.data_ptr(), ws.data_ptr(), need,
                                    _stream(A.device))
     N.check(st, "perm_dense_f64_ex")
     return out
+
+
+def dense_f64_launches(n: int, accumulation: int = ACC_TWOSUM, log2_reseed: int = 0,
+                       max_steps_per_launch: int = 0, log2_lanes: int = 0) -> int:
+    """Number of launches perm_dense_f64_ex splits the sweep of order n into."""
+    opt = PermOptions(accumulation, log2_reseed, max_steps_per_launch, log2_lanes, 0, 0)
+    r = int(N.lib().perm_dense_f64_launches(n, ctypes.byref(opt)))
+    N.check(r if r < 0 else 0, "perm_dense_f64_launches")
+    return r
 
 
 def perm_dense_c128(A: torch.Tensor, out: torch.Tensor | None = None, ws=None) -> torch.Tensor:

@@ -241,24 +241,43 @@ int perm_dense_f64(int n, const double *A, int64_t lda, double *out, void *ws, s
                             static_cast<hipStream_t>(stream));
 }
 
+// perm_options -> SweepOptions; false for invalid options.
+static bool sweep_options(int n, const perm_options *opt, SweepOptions &o)
+{
+    o = default_sweep_options(n);
+    if (!opt) return true;
+    if (opt->accumulation != PERM_ACC_TWOSUM && opt->accumulation != PERM_ACC_PLAIN &&
+        opt->accumulation != PERM_ACC_KAHAN)
+        return false;
+    if (opt->log2_reseed < 0 || opt->log2_reseed > 62 || opt->max_steps_per_launch < 0 ||
+        opt->log2_lanes < 0 || opt->log2_lanes > 40 || opt->first_launch < 0 ||
+        opt->launch_count < 0)
+        return false;
+    o.log2_lanes = opt->log2_lanes;
+    o.accumulation = opt->accumulation;
+    if (opt->log2_reseed > 0) o.log2_reseed = opt->log2_reseed;
+    if (opt->max_steps_per_launch > 0) o.max_steps_per_launch = opt->max_steps_per_launch;
+    o.first_launch = opt->first_launch;
+    o.launch_count = opt->launch_count;
+    return true;
+}
+
+int64_t perm_dense_f64_launches(int n, const perm_options *opt)
+{
+    if (!valid_n(n)) return PERM_EINVAL;
+    SweepOptions o;
+    if (!sweep_options(n, opt, o)) return PERM_EINVAL;
+    return n == 0 ? 1 : dense_f64_launches(n, o);
+}
+
 int perm_dense_f64_ex(int n, const double *A, int64_t lda, const perm_options *opt, double *out,
                       void *ws, size_t ws_bytes, void *stream)
 {
     if (!valid_n(n) || !out) return PERM_EINVAL;
     if (n > 0 && (!A || lda < n)) return PERM_EINVAL;
-    SweepOptions o = default_sweep_options(n);
-    if (opt) {
-        if (opt->accumulation != PERM_ACC_TWOSUM && opt->accumulation != PERM_ACC_PLAIN &&
-            opt->accumulation != PERM_ACC_KAHAN)
-            return PERM_EINVAL;
-        if (opt->log2_reseed < 0 || opt->log2_reseed > 62 || opt->max_steps_per_launch < 0 ||
-            opt->log2_lanes < 0 || opt->log2_lanes > 40)
-            return PERM_EINVAL;
-        o.log2_lanes = opt->log2_lanes;
-        o.accumulation = opt->accumulation;
-        if (opt->log2_reseed > 0) o.log2_reseed = opt->log2_reseed;
-        if (opt->max_steps_per_launch > 0) o.max_steps_per_launch = opt->max_steps_per_launch;
-    }
+    SweepOptions o;
+    if (!sweep_options(n, opt, o)) return PERM_EINVAL;
+    if (o.first_launch >= (n == 0 ? 1 : dense_f64_launches(n, o))) return PERM_EINVAL;
     const int w = check_ws(ws, ws_bytes, perm_workspace_bytes(PERM_KIND_DENSE_F64, n, 0));
     if (w != PERM_OK) return w;
     return launch_dense_f64_opt(n, A, lda, out, o, static_cast<char *>(ws),

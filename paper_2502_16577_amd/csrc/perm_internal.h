@@ -71,6 +71,8 @@ struct SweepOptions {
     int log2_reseed = 9;                            // exact re-seed every 2^r steps (<= c)
     int64_t max_steps_per_launch = int64_t(1) << 40;  // split longer sweeps into launches
     int log2_lanes = 0;                             // 0 = plan_sweep's choice
+    int64_t first_launch = 0;                       // run launches [first, first + count)
+    int64_t launch_count = 0;                       // 0 = through the last one
 };
 
 inline SweepOptions default_sweep_options(int n)
@@ -203,6 +205,10 @@ int launch_dense_f64(int n, const double *A, int64_t lda, double *out, char *ws,
                      hipStream_t stream);
 int launch_dense_f64_opt(int n, const double *A, int64_t lda, double *out, const SweepOptions &o,
                          char *ws, hipStream_t stream);
+// The dense sweep's plan under the options, and the number of launches the
+// sweep is split into (1 for n <= 12).
+SweepPlan dense_plan(int n, const SweepOptions &o);
+int64_t dense_f64_launches(int n, const SweepOptions &o);
 int launch_dense_c128(int n, const perm_c128 *A, int64_t lda, perm_c128 *out, char *ws,
                       hipStream_t stream);
 // Permanent and dperm/dA (row-major n x n, interleaved if complex).

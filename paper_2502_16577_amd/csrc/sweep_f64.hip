@@ -174,23 +174,37 @@ __global__ __launch_bounds__(kBlock) void sweep_dense_f64(const double *__restri
     if (threadIdx.x == 0) partials[blockIdx.x] = accumulate ? dd_add(partials[blockIdx.x], t) : t;
 }
 
-// Launches the sweep over the full grid, as consecutive ranges of each
-// lane's chunk of at most max_steps_per_launch subset-steps per launch (one
-// launch for the usual sizes).  Every range starts on a re-seed boundary.
+// Chunk steps per launch: the sweep runs over the full grid as consecutive
+// ranges of each lane's chunk of at most max_steps_per_launch subset-steps
+// per launch (one launch for the usual sizes); a power-of-two number of
+// re-seed intervals (and blocks), so every range is whole and starts on a
+// re-seed boundary.
+int64_t dense_launch_span(int n, const SweepPlan &p, const SweepOptions &o)
+{
+    const int64_t C = int64_t(1) << p.log2_chunk;
+    int64_t span = o.max_steps_per_launch / p.lanes;
+    const int64_t unit = std::max<int64_t>(int64_t(1) << o.log2_reseed, 1 << (n >= 14 ? 4 : 3));
+    span = std::max(unit, span - span % unit);
+    int64_t pow2 = unit;
+    while (pow2 * 2 <= span && pow2 * 2 <= C) pow2 *= 2;
+    return std::min(pow2, C);
+}
+
+// Launches [o.first_launch, o.first_launch + o.launch_count) of the sweep
+// (all of them for launch_count 0); launch i covers steps [i span, (i+1) span)
+// of every lane's chunk and adds to the partials of launches before it.
 template <int N>
 static void launch_sweep_n(const SweepPlan &p, const SweepOptions &o, const double *acol,
                            const double *aneg, const double *x0, dd *partials,
                            hipStream_t stream)
 {
     const int64_t C = int64_t(1) << p.log2_chunk;
-    int64_t span = o.max_steps_per_launch / p.lanes;  // chunk steps per launch
-    const int64_t unit = std::max<int64_t>(int64_t(1) << o.log2_reseed, 1 << dense_unroll<N>());
-    span = std::max(unit, span - span % unit);
-    // a power-of-two number of units divides C, so every range is whole
-    int64_t pow2 = unit;
-    while (pow2 * 2 <= span && pow2 * 2 <= C) pow2 *= 2;
-    span = std::min(pow2, C);
-    for (int64_t l0 = 0; l0 < C; l0 += span) {
+    const int64_t span = dense_launch_span(N, p, o);
+    const int64_t nl = C / span;
+    const int64_t first = std::min(o.first_launch, nl);
+    const int64_t end = o.launch_count > 0 ? std::min(nl, first + o.launch_count) : nl;
+    for (int64_t i = first; i < end; ++i) {
+        const int64_t l0 = i * span;
         const uint32_t lb = uint32_t(l0), le = uint32_t(l0 + span);
         const int accumulate = l0 > 0;
         if (o.accumulation == kAccTwoSum)
@@ -234,15 +248,11 @@ int launch_dense_f64(int n, const double *A, int64_t lda, double *out, char *ws,
     return launch_dense_f64_opt(n, A, lda, out, default_sweep_options(n), ws, stream);
 }
 
-int launch_dense_f64_opt(int n, const double *A, int64_t lda, double *out, const SweepOptions &o,
-                         char *ws, hipStream_t stream)
+// The dense sweep's plan under the options: plan_sweep's, or the lane count
+// of o.log2_lanes clamped to [2^8, max(2^18, default)], to chunks longer than
+// the block (c > U) and to chunks of at most 2^31 steps.
+SweepPlan dense_plan(int n, const SweepOptions &o)
 {
-    // The workspace holds block partials for max(default, 2^18 lanes); other
-    // lane counts are clamped to that.
-    if (n == 0) {
-        hipLaunchKernelGGL(write_one_f64, dim3(1), dim3(1), 0, stream, out);
-        return hipGetLastError() == hipSuccess ? PERM_OK : PERM_EHIP;
-    }
     SweepPlan p = plan_sweep(n, 0);
     if (o.log2_lanes > 0 && n > kSmallN) {
         const int total = n - 1;
@@ -259,6 +269,28 @@ int launch_dense_f64_opt(int n, const double *A, int64_t lda, double *out, const
         p.blocks = p.lanes / kBlock;
         if (p.log2_reseed > p.log2_chunk) p.log2_reseed = p.log2_chunk;
     }
+    return p;
+}
+
+int64_t dense_f64_launches(int n, const SweepOptions &o)
+{
+    if (n <= kSmallN) return 1;
+    const SweepPlan p = dense_plan(n, o);
+    SweepOptions oo = o;
+    if (oo.log2_reseed < 1 || oo.log2_reseed > p.log2_chunk) oo.log2_reseed = p.log2_chunk;
+    return (int64_t(1) << p.log2_chunk) / dense_launch_span(n, p, oo);
+}
+
+int launch_dense_f64_opt(int n, const double *A, int64_t lda, double *out, const SweepOptions &o,
+                         char *ws, hipStream_t stream)
+{
+    // The workspace holds block partials for max(default, 2^18 lanes); other
+    // lane counts are clamped to that.
+    if (n == 0) {
+        hipLaunchKernelGGL(write_one_f64, dim3(1), dim3(1), 0, stream, out);
+        return hipGetLastError() == hipSuccess ? PERM_OK : PERM_EHIP;
+    }
+    const SweepPlan p = dense_plan(n, o);
     const DenseWs L = dense_ws_layout(n, 1, dense_ws_blocks(n));
     double *acol = reinterpret_cast<double *>(ws + L.acol);
     double *aneg = reinterpret_cast<double *>(ws + L.aneg);

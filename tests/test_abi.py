@@ -188,6 +188,19 @@ def test_dense_ex_option_errors():
     assert lib.perm_dense_f64_ex(20, FAKE, 20, ctypes.byref(bad), FAKE, FAKE, big, None) == N.PERM_EINVAL
     ok = PermOptions(1, 4, 1 << 20, 12)
     assert lib.perm_dense_f64_ex(20, FAKE, 20, ctypes.byref(ok), FAKE, None, 0, None) == N.PERM_EWORKSPACE
+    # launch ranges: n = 26 (2^18 lanes of 128 steps) with 16-step re-seeds and
+    # at most 2^22 subset-steps per launch is 8 launches; a range starting at
+    # or beyond the last, or a negative field, is refused before any GPU work
+    split = PermOptions(0, 4, 1 << 22, 0)
+    assert lib.perm_dense_f64_launches(26, ctypes.byref(split)) == 8
+    assert lib.perm_dense_f64_launches(26, None) == 1
+    assert lib.perm_dense_f64_launches(8, ctypes.byref(split)) == 1
+    assert lib.perm_dense_f64_launches(-1, None) == N.PERM_EINVAL
+    beyond = PermOptions(0, 4, 1 << 22, 0, 8, 1)
+    assert lib.perm_dense_f64_ex(26, FAKE, 26, ctypes.byref(beyond), FAKE, FAKE, big, None) == N.PERM_EINVAL
+    for neg in (PermOptions(0, 4, 1 << 22, 0, -1, 0), PermOptions(0, 4, 1 << 22, 0, 0, -1)):
+        assert lib.perm_dense_f64_ex(26, FAKE, 26, ctypes.byref(neg), FAKE, FAKE, big, None) == N.PERM_EINVAL
+        assert lib.perm_dense_f64_launches(26, ctypes.byref(neg)) == N.PERM_EINVAL
 
 
 def test_binary_empty_matrix_on_the_host():

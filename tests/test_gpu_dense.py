@@ -247,3 +247,23 @@ def test_options_at_small_orders(oracle, n):
                 assert abs(v - want) <= 1e-10 * abs(want), (ll, r, acc, v, want)
     v = api.perm_dense_f64_ex(A, max_steps_per_launch=1 << 8).item()
     assert abs(v - want) <= 1e-10 * abs(want)
+
+
+def test_split_sweep_over_several_calls(oracle):
+    # the 8 launches of a split sweep run by one call, by eight calls of one
+    # launch and by three calls of 3 + 3 + 2 launches (same workspace): the
+    # same value bit for bit, and the oracle's value within tolerance
+    a = W.uniform(26, 77)
+    A = torch.from_numpy(a).to(DEV)
+    opts = dict(log2_reseed=4, max_steps_per_launch=1 << 22)
+    nl = api.dense_f64_launches(26, **opts)
+    assert nl == 8
+    ws = torch.empty(api.workspace_bytes(1, 26), dtype=torch.uint8, device=DEV)
+    one = api.perm_dense_f64_ex(A, ws=ws, **opts).item()
+    for ranges in ([(i, 1) for i in range(8)], [(0, 3), (3, 3), (6, 2)], [(0, 5), (5, 0)]):
+        out = torch.empty((), dtype=torch.float64, device=DEV)
+        for first, count in ranges:
+            api.perm_dense_f64_ex(A, first_launch=first, launch_count=count, out=out, ws=ws, **opts)
+        assert out.item() == one, ranges
+    want = oracle.ryser(a)
+    assert abs(one - want) <= 1e-10 * abs(want)
