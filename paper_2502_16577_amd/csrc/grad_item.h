@@ -29,8 +29,8 @@
 // MFMA operand layout (gfx950): A[i][k] at lane i + 16k, B[k][j] at lane
 // j + 16k, D[i][j] at lane j + 16 (i mod 4), register i / 4.
 // Accumulators fold into the item's double-double partial G in global memory
-// at the end of every window (2^7 steps at most, so plain FP64 accumulation
-// never spans more than 128 steps of 64 subsets).
+// at the end of every window (2^9 steps at most, so plain FP64 accumulation
+// never spans more than 512 steps of 64 subsets).
 //
 // Staged layout: acol / aneg hold column j at [W (j NP + i)] with NP = NS R
 // rows (rows >= n are zero) and x0 has NP entries (1 for rows >= n), so a
@@ -109,7 +109,7 @@ __device__ __forceinline__ void grad_item(const double *__restrict__ acol,
     double *xbuf = lds + NS * S::VBUF;
     const uint32_t C = 1u << c;
     const uint32_t rmask = (1u << r) - 1u;
-    const int f = c - 1 < 7 ? c - 1 : 7;  // window = 2^f steps
+    const int f = c - 1 < 9 ? c - 1 : 9;  // window = 2^f steps
     const uint32_t fmask = (1u << f) - 1u;
     const uint64_t Kl = w * kWave + lane;
     const double act = Kl < lanes_active ? 1.0 : 0.0;

@@ -9,7 +9,7 @@
 // division, so zeros in x are harmless) and contracts V = (-1)^g L with tau
 // on FP64 MFMA, organised by Gray-code windows (grad_item.h).  Each block of
 // two waves covers 64 subsets; the waves split the rows.  The MFMA
-// accumulators are folded at the end of every window (at most 128 steps)
+// accumulators are folded at the end of every window (at most 512 steps)
 // into per-item double-double accumulators in global memory.
 #include "grad_item.h"
 
