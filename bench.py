@@ -446,7 +446,7 @@ def main():
                                        baselines=not args.batched_quick)), flush=True)
         return
     if args.gpus != 1:
-        print("bench.py: this build runs on exactly one GPU (no multi-GPU path); use --gpus 1",
+        print("bench.py: one GPU only (the library has no multi-GPU path); use --gpus 1",
               file=sys.stderr)
         sys.exit(2)
 

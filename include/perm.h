@@ -58,7 +58,7 @@ typedef struct {
 #define PERM_ERANGE       -2  /* result would not fit (binary: bound above the CRT modulus) */
 #define PERM_EWORKSPACE   -3  /* ws NULL or ws_bytes below perm_workspace_bytes() */
 #define PERM_EHIP         -4  /* a HIP runtime call failed */
-#define PERM_EUNSUPPORTED -5  /* valid request this build does not implement */
+#define PERM_EUNSUPPORTED -5  /* valid request the library does not implement */
 #define PERM_ECOMPILE     -6  /* run-time compilation of a generated kernel failed */
 
 /* Workspace kinds for perm_workspace_bytes(). */

@@ -2,10 +2,9 @@
 finite differences.
 
 Gradient tolerances: |G - minors| <= 1e-10 * perm(|minor|) entrywise (the
-scale the benchmark spec fixes for signed / complex entries; relative 1e-10 for
-positive entries), and the same R-based gate as the permanent:
-|G - minors| <= 1e-12 * 2^(n-1) * max|L| is not used; instead Laplace's
-identity sum_j a_ij G_ij = perm(A) is checked on every row and column.
+scale used for signed / complex permanents; relative 1e-10 for positive
+entries); instead of an R-based gate on each entry, Laplace's identity
+sum_j a_ij G_ij = perm(A) is checked on every row and column.
 Finite differences: max |G - FD| <= 1e-6 * max |FD| (FD from the oracle,
 exact for an affine map up to rounding).
 """
