@@ -61,8 +61,8 @@ def _declare(lib):
         f.argtypes = [c_int, dp, c_int, dp, dp]
     lib.orc_ryser_real_sample.restype = c_int
     lib.orc_ryser_real_sample.argtypes = [c_int, dp, c_int, ctypes.c_uint64, ctypes.c_uint64, dp]
-    lib.orc_sparyser_real.restype = c_int
-    lib.orc_sparyser_real.argtypes = [c_int, i32p, i32p, dp, i32p, i32p, dp, dp]
+    lib.orc_ryser_csc_real.restype = c_int
+    lib.orc_ryser_csc_real.argtypes = [c_int, i32p, i32p, dp, c_int, dp, dp]
     lib.orc_ryser_binary.restype = c_int
     lib.orc_ryser_binary.argtypes = [c_int, u8p, c_int, u64p, u64p]
     lib.orc_matchings_dp.restype = c_int
@@ -183,29 +183,36 @@ class Oracle:
     CHUNK_STEPS = 4096
 
     # -- Algorithm 2 ----------------------------------------------------------
-    def sparyser(self, a):
-        r = _real(a)
-        n = r.shape[0]
-        rows, cols = np.nonzero(r)
-        order_r = np.lexsort((cols, rows))
-        rptrs = np.zeros(n + 1, np.int32)
-        np.add.at(rptrs, rows + 1, 1)
-        rptrs = np.cumsum(rptrs).astype(np.int32)
-        cids = cols[order_r].astype(np.int32)
-        rvals = r[rows[order_r], cols[order_r]].astype(np.float64)
-        order_c = np.lexsort((rows, cols))
-        cptrs = np.zeros(n + 1, np.int32)
-        np.add.at(cptrs, cols + 1, 1)
-        cptrs = np.cumsum(cptrs).astype(np.int32)
-        rids = rows[order_c].astype(np.int32)
-        cvals = r[rows[order_c], cols[order_c]].astype(np.float64)
+    def ryser_csc(self, n: int, col_ptr, row_idx, vals, threads: int = 0,
+                  with_abs: bool = False):
+        """perm of a real matrix given by CSC columns (Algorithm 2: a step
+        updates x by the flipped column's nonzeros only), long double."""
+        col_ptr = np.ascontiguousarray(col_ptr, dtype=np.int32)
+        row_idx = np.ascontiguousarray(row_idx, dtype=np.int32)
+        vals = np.ascontiguousarray(vals, dtype=np.float64)
+        if col_ptr.size != n + 1 or row_idx.size != vals.size:
+            raise ValueError("malformed CSC")
         i32 = ctypes.POINTER(ctypes.c_int32)
         out = np.zeros(2)
-        _check(self.lib.orc_sparyser_real(
-            n, rptrs.ctypes.data_as(i32), cids.ctypes.data_as(i32), _dptr(rvals),
-            cptrs.ctypes.data_as(i32), rids.ctypes.data_as(i32), _dptr(cvals), _dptr(out)),
-            "sparyser_real")
-        return float(out[0] + out[1])
+        absum = np.zeros(2)
+        _check(self.lib.orc_ryser_csc_real(
+            n, col_ptr.ctypes.data_as(i32), row_idx.ctypes.data_as(i32), _dptr(vals), threads,
+            _dptr(out), _dptr(absum)), "ryser_csc_real")
+        v = float(out[0] + out[1])
+        return (v, float(absum[0] + absum[1])) if with_abs else v
+
+    def sparse(self, a, threads: int = 0):
+        """ryser_csc of the nonzeros of a dense real matrix."""
+        r = _real(a)
+        n = r.shape[0]
+        col_ptr = np.zeros(n + 1, np.int32)
+        rows, vals = [], []
+        for j in range(n):
+            nz = np.nonzero(r[:, j])[0]
+            rows.extend(nz.tolist())
+            vals.extend(r[nz, j].tolist())
+            col_ptr[j + 1] = len(rows)
+        return self.ryser_csc(n, col_ptr, rows, vals, threads)
 
     # -- exact binary ---------------------------------------------------------
     def binary(self, a01, threads: int = 0, with_nonzero: bool = False):

@@ -26,9 +26,12 @@
  *                                         (each chunk re-derives x from the
  *                                         Gray code of the step before it).
  *                                         Also returns R(A) = 2 * sum_g |term_g|.
- *   orc_sparyser_real                     Algorithm 2 (SpaRyser on CRS + CCS)
- *                                         with the column update of x that the
- *                                         printed algorithm omits.
+ *   orc_ryser_csc_real                    Algorithm 2 (SpaRyser): the same walk
+ *                                         on a matrix given by its columns in
+ *                                         CSC form, where a step adds only the
+ *                                         nonzeros of the flipped column to x
+ *                                         (Section 2.1; the printed algorithm
+ *                                         leaves this update out).
  *   orc_ryser_binary                      Algorithm 2 on a 0/1 matrix in exact
  *                                         integers: y = 2x is integral, every
  *                                         term is an exact 384-bit integer, and
@@ -243,7 +246,9 @@ int orc_inclexcl_cplx(int n, const double *a, double out[4])
 
 typedef struct {
     int n, cplx;
-    const double *a;
+    const double *a;        /* dense row-major matrix, or NULL when csc_* is given */
+    const int32_t *csc_ptr, *csc_row;   /* CSC columns (real only) */
+    const double *csc_val;
     ld *x0r, *x0i;          /* Nijenhuis-Wilf start vector */
     uint64_t steps;         /* 2^(n-1) - 1 loop iterations */
     uint64_t nitems, chunks_per_item;
@@ -252,6 +257,42 @@ typedef struct {
     uint64_t first_chunk;   /* chunk index of item 0 (0 except for samples) */
 } ryser_job_t;
 
+/* x += sign * column j of the matrix (every row for a dense matrix, the
+ * column's nonzeros for a CSC one). */
+static inline void add_column(const ryser_job_t *J, int j, int sign, ld *xr, ld *xi)
+{
+    const int n = J->n;
+    if (J->csc_ptr) {
+        const int32_t q0 = J->csc_ptr[j], q1 = J->csc_ptr[j + 1];
+        if (sign > 0)
+            for (int32_t q = q0; q < q1; q++) xr[J->csc_row[q]] += J->csc_val[q];
+        else
+            for (int32_t q = q0; q < q1; q++) xr[J->csc_row[q]] -= J->csc_val[q];
+#if ORC_MUTANT == 11
+        if (q1 > q0)                               /* loses the column's first nonzero */
+            xr[J->csc_row[q0]] -= sign * (ld)J->csc_val[q0];
+#endif
+        return;
+    }
+    if (J->cplx) {
+        const double *c = J->a;
+        if (sign > 0)
+            for (int i = 0; i < n; i++) { xr[i] += c[2 * (i * n + j)]; xi[i] += c[2 * (i * n + j) + 1]; }
+        else
+            for (int i = 0; i < n; i++) { xr[i] -= c[2 * (i * n + j)]; xi[i] -= c[2 * (i * n + j) + 1]; }
+        return;
+    }
+#if ORC_MUTANT == 4
+    const int rs = 1, cs = n;                      /* transposed operand */
+#else
+    const int rs = n, cs = 1;                      /* a_ij at a[i * n + j] */
+#endif
+    if (sign > 0)
+        for (int i = 0; i < n; i++) xr[i] += J->a[i * rs + j * cs];
+    else
+        for (int i = 0; i < n; i++) xr[i] -= J->a[i * rs + j * cs];
+}
+
 static void ryser_range(const ryser_job_t *J, uint64_t start, uint64_t end,
                         kahan_t *kre, kahan_t *kim, ld *abs_sum)
 {
@@ -259,15 +300,11 @@ static void ryser_range(const ryser_job_t *J, uint64_t start, uint64_t end,
     const int n = J->n;
     ld xr[64], xi[64];
     for (int i = 0; i < n; i++) { xr[i] = J->x0r[i]; xi[i] = J->cplx ? J->x0i[i] : 0; }
-    /* Set x to the state of the previous Gray code (Algorithm 3). */
+    /* x of the subset Gray_{start-1}, rebuilt from the start vector
+     * (Algorithm 3: every chunk begins from a freshly derived state). */
     uint64_t gp = orc_gray(start - 1);
-    for (int j = 0; j < n - 1; j++) {
-        if (!((gp >> j) & 1)) continue;
-        for (int i = 0; i < n; i++) {
-            if (J->cplx) { xr[i] += J->a[2 * (i * n + j)]; xi[i] += J->a[2 * (i * n + j) + 1]; }
-            else xr[i] += J->a[i * n + j];
-        }
-    }
+    for (int j = 0; j < n - 1; j++)
+        if ((gp >> j) & 1) add_column(J, j, 1, xr, xi);
     for (uint64_t g = start; g <= end; g++) {
         int j = orc_flip_col(g);
         int s = orc_flip_sign(g);
@@ -277,30 +314,29 @@ static void ryser_range(const ryser_job_t *J, uint64_t start, uint64_t end,
 #if ORC_MUTANT == 3
         if (j > 0) j = j - 1;                     /* wrong column index */
 #endif
+        add_column(J, j, s, xr, xi);
         ld pr = 1, pi = 0;
-        for (int i = 0; i < n; i++) {
-            if (J->cplx) {
-                xr[i] += s * (ld)J->a[2 * (i * n + j)];
-                xi[i] += s * (ld)J->a[2 * (i * n + j) + 1];
+        if (J->cplx) {
+            for (int i = 0; i < n; i++) {
                 ld nr = pr * xr[i] - pi * xi[i];
                 ld ni = pr * xi[i] + pi * xr[i];
 #if ORC_MUTANT == 6
                 ni = pr * xi[i] - pi * xr[i];     /* conjugation slip */
 #endif
                 pr = nr; pi = ni;
-            } else {
-#if ORC_MUTANT == 4
-                xr[i] += s * (ld)J->a[j * n + i]; /* transposed operand */
-#else
-                xr[i] += s * (ld)J->a[i * n + j];
-#endif
-                pr *= xr[i];
             }
+        } else {
+            for (int i = 0; i < n; i++) pr *= xr[i];
         }
         if (g & 1) { pr = -pr; pi = -pi; }         /* (-1)^g */
         kahan_add(kre, pr);
         if (J->cplx) kahan_add(kim, pi);
+#if ORC_MUTANT == 10
+        *abs_sum += J->cplx ? (pr < 0 ? -pr : pr) + (pi < 0 ? -pi : pi)   /* |re| + |im| */
+                            : (pr < 0 ? -pr : pr);
+#else
         *abs_sum += J->cplx ? __builtin_sqrtl(pr * pr + pi * pi) : (pr < 0 ? -pr : pr);
+#endif
     }
 }
 
@@ -330,6 +366,64 @@ static void *ryser_worker(void *arg)
     return NULL;
 }
 
+/* Runs steps 1 .. 2^(n-1)-1 of the walk of job J (x0r / x0i set) over
+ * nthreads threads, adds the g = 0 term prod_i x0_i, and writes
+ * 2 (-1)^(n-1) times the sum (Algorithm 1's final factor 4 (n mod 2) - 2)
+ * and R(A) = 2 sum_g |term_g|. */
+static int walk_all(ryser_job_t *J, int nthreads, double out[4], double absum[2])
+{
+    const int n = J->n, cplx = J->cplx;
+    /* the empty subset's term (g = 0): the product of the start vector */
+    ld p0r = 1, p0i = 0;
+    for (int i = 0; i < n; i++) {
+        ld nr = p0r * J->x0r[i] - p0i * J->x0i[i];
+        ld ni = p0r * J->x0i[i] + p0i * J->x0r[i];
+        p0r = nr; p0i = ni;
+    }
+    J->steps = (1ull << (n - 1)) - 1;
+    uint64_t nchunks = (J->steps + ORC_CHUNK - 1) / ORC_CHUNK;
+    J->chunks_per_item = 1;
+    while (nchunks / J->chunks_per_item > (1ull << 16)) J->chunks_per_item <<= 1;
+    J->nitems = (nchunks + J->chunks_per_item - 1) / J->chunks_per_item;
+    size_t nb = (J->nitems ? J->nitems : 1) * sizeof(ld);
+    J->item_re = (ld *)calloc(1, nb);
+    J->item_im = (ld *)calloc(1, nb);
+    J->item_abs = (ld *)calloc(1, nb);
+    if (!J->item_re || !J->item_im || !J->item_abs) {
+        free(J->item_re); free(J->item_im); free(J->item_abs);
+        return -1;
+    }
+    int T = default_threads(nthreads);
+    if ((uint64_t)T > J->nitems) T = J->nitems ? (int)J->nitems : 1;
+    if (T > 256) T = 256;
+    pthread_t th[256];
+    int ok[256] = {0};
+    for (int t = 1; t < T; t++) ok[t] = pthread_create(&th[t], NULL, ryser_worker, J) == 0;
+    ryser_worker(J);
+    for (int t = 1; t < T; t++) if (ok[t]) pthread_join(th[t], NULL);
+
+    kahan_t kre = {0, 0}, kim = {0, 0};
+    kahan_add(&kre, p0r);
+    kahan_add(&kim, p0i);
+    ld abs_sum = cplx ? __builtin_sqrtl(p0r * p0r + p0i * p0i) : (p0r < 0 ? -p0r : p0r);
+    for (uint64_t it = 0; it < J->nitems; it++) {
+        kahan_add(&kre, J->item_re[it]);
+        kahan_add(&kim, J->item_im[it]);
+        abs_sum += J->item_abs[it];
+    }
+    free(J->item_re); free(J->item_im); free(J->item_abs);
+
+    ld f = (n & 1) ? 2 : -2;                    /* 2 (-1)^(n-1) */
+    ld_split(f * (kre.s - kre.c), out);
+    if (cplx) ld_split(f * (kim.s - kim.c), out + 2);
+#if ORC_MUTANT == 9
+    if (absum) ld_split(abs_sum, absum);        /* loses the factor 2 */
+#else
+    if (absum) ld_split(2 * abs_sum, absum);
+#endif
+    return 0;
+}
+
 static int ryser_common(int n, const double *a, int cplx, int nthreads,
                         double out[4], double absum[2])
 {
@@ -342,7 +436,8 @@ static int ryser_common(int n, const double *a, int cplx, int nthreads,
         return 0;
     }
     ld x0r[64], x0i[64];
-    /* Lines 1-4 of Algorithm 1: x_i = a_{i,n} - (row sum)/2. */
+    /* Algorithm 1's start vector: x_i = a_{i,n} - (row sum)/2, with a_{i,n}
+     * the entry in the last (never flipped) column. */
     for (int i = 0; i < n; i++) {
         ld sr = 0, si = 0;
         for (int j = 0; j < n; j++) {
@@ -361,56 +456,10 @@ static int ryser_common(int n, const double *a, int cplx, int nthreads,
             x0i[i] = 0;
         }
     }
-    /* p <- prod_i x_i (empty subset; g = 0). */
-    ld p0r = 1, p0i = 0;
-    for (int i = 0; i < n; i++) {
-        ld nr = p0r * x0r[i] - p0i * x0i[i];
-        ld ni = p0r * x0i[i] + p0i * x0r[i];
-        p0r = nr; p0i = ni;
-    }
-
     ryser_job_t J;
     memset(&J, 0, sizeof J);
     J.n = n; J.cplx = cplx; J.a = a; J.x0r = x0r; J.x0i = x0i;
-    J.steps = (n >= 1) ? ((1ull << (n - 1)) - 1) : 0;
-    uint64_t nchunks = (J.steps + ORC_CHUNK - 1) / ORC_CHUNK;
-    J.chunks_per_item = 1;
-    while (nchunks / J.chunks_per_item > (1ull << 16)) J.chunks_per_item <<= 1;
-    J.nitems = (nchunks + J.chunks_per_item - 1) / J.chunks_per_item;
-    size_t nb = (J.nitems ? J.nitems : 1) * sizeof(ld);
-    J.item_re = (ld *)calloc(1, nb);
-    J.item_im = (ld *)calloc(1, nb);
-    J.item_abs = (ld *)calloc(1, nb);
-    if (!J.item_re || !J.item_im || !J.item_abs) {
-        free(J.item_re); free(J.item_im); free(J.item_abs);
-        return -1;
-    }
-    int T = default_threads(nthreads);
-    if ((uint64_t)T > J.nitems) T = J.nitems ? (int)J.nitems : 1;
-    if (T > 256) T = 256;
-    pthread_t th[256];
-    int ok[256] = {0};
-    for (int t = 1; t < T; t++) ok[t] = pthread_create(&th[t], NULL, ryser_worker, &J) == 0;
-    ryser_worker(&J);
-    for (int t = 1; t < T; t++) if (ok[t]) pthread_join(th[t], NULL);
-
-    kahan_t kre = {0, 0}, kim = {0, 0};
-    kahan_add(&kre, p0r);
-    kahan_add(&kim, p0i);
-    ld abs_sum = cplx ? __builtin_sqrtl(p0r * p0r + p0i * p0i) : (p0r < 0 ? -p0r : p0r);
-    for (uint64_t it = 0; it < J.nitems; it++) {
-        kahan_add(&kre, J.item_re[it]);
-        kahan_add(&kim, J.item_im[it]);
-        abs_sum += J.item_abs[it];
-    }
-    free(J.item_re); free(J.item_im); free(J.item_abs);
-
-    /* Return p * (4 (n mod 2) - 2) = 2 (-1)^(n-1) p. */
-    ld f = (n & 1) ? 2 : -2;
-    ld_split(f * (kre.s - kre.c), out);
-    if (cplx) ld_split(f * (kim.s - kim.c), out + 2);
-    if (absum) ld_split(2 * abs_sum, absum);
-    return 0;
+    return walk_all(&J, nthreads, out, absum);
 }
 
 int orc_ryser_real(int n, const double *a, int nthreads, double out[2], double absum[2])
@@ -473,42 +522,51 @@ int orc_ryser_real_sample(int n, const double *a, int nthreads, uint64_t first_c
 }
 
 /* ------------------------------------------------------------------------ */
-/* Algorithm 2 (SpaRyser) for a real matrix given in CRS and CCS             */
+/* Algorithm 2 (SpaRyser): the walk on CSC columns                          */
 /* ------------------------------------------------------------------------ */
 
-/* Single-threaded, n <= 30.  rptrs/cids/rvals: CRS; cptrs/rids/cvals: CCS. */
-int orc_sparyser_real(int n, const int32_t *rptrs, const int32_t *cids, const double *rvals,
-                      const int32_t *cptrs, const int32_t *rids, const double *cvals,
-                      double out[2])
+/*
+ * Permanent of a real n x n matrix given by its columns in CSC form
+ * (col_ptr[n+1], row_idx[nnz], vals[nnz]; duplicates are not allowed).  The
+ * row sums and the entries of the last column come from the stored
+ * nonzeros; each step of the Gray walk adds or subtracts only the nonzeros
+ * of the flipped column, and the product still runs over every row.  The
+ * result equals orc_ryser_real on the dense form of the same matrix.
+ */
+int orc_ryser_csc_real(int n, const int32_t *col_ptr, const int32_t *row_idx,
+                       const double *vals, int nthreads, double out[2], double absum[2])
 {
-    if (n < 1 || n > 30 || !rptrs || !cids || !rvals || !cptrs || !rids || !cvals || !out)
-        return -1;
-    ld x[64];
-    for (int i = 0; i < n; i++) {
-        ld sum = 0, last = 0;
-        for (int32_t p = rptrs[i]; p < rptrs[i + 1]; p++) {
-            sum += rvals[p];
-            if (cids[p] == n - 1) last = rvals[p];
+    if (n < 0 || n > 63 || !out || (n > 0 && !col_ptr)) return -1;
+    if (n == 0) {
+        out[0] = 1.0; out[1] = 0.0;
+        if (absum) { absum[0] = 1.0; absum[1] = 0.0; }
+        return 0;
+    }
+    if (col_ptr[0] != 0) return -1;
+    for (int j = 0; j < n; j++) {
+        if (col_ptr[j + 1] < col_ptr[j]) return -1;
+        for (int32_t q = col_ptr[j]; q < col_ptr[j + 1]; q++)
+            if (row_idx[q] < 0 || row_idx[q] >= n) return -1;
+    }
+    /* row sums and last-column entries, columns taken in ascending order
+     * (the dense oracle's order of summation; absent entries are zeros) */
+    ld rsum[64], last[64], x0r[64], x0i[64];
+    for (int i = 0; i < n; i++) { rsum[i] = 0; last[i] = 0; x0i[i] = 0; }
+    for (int j = 0; j < n; j++)
+        for (int32_t q = col_ptr[j]; q < col_ptr[j + 1]; q++) {
+            rsum[row_idx[q]] += vals[q];
+            if (j == n - 1) last[row_idx[q]] = vals[q];
         }
-        x[i] = last - sum / 2;
-    }
-    kahan_t acc = {0, 0};
-    ld prod = 1;
-    for (int i = 0; i < n; i++) prod *= x[i];
-    kahan_add(&acc, prod);
-    uint64_t steps = 1ull << (n - 1);
-    for (uint64_t g = 1; g < steps; g++) {
-        int j = orc_flip_col(g);
-        int s = orc_flip_sign(g);
-        for (int32_t p = cptrs[j]; p < cptrs[j + 1]; p++)
-            x[rids[p]] += s * (ld)cvals[p];       /* the update the listing omits */
-        prod = 1;
-        for (int i = 0; i < n; i++) prod *= x[i];
-        kahan_add(&acc, (g & 1) ? -prod : prod);
-    }
-    ld f = (n & 1) ? 2 : -2;
-    ld_split(f * (acc.s - acc.c), out);
-    return 0;
+    for (int i = 0; i < n; i++) x0r[i] = last[i] - rsum[i] / 2;
+    ryser_job_t J;
+    memset(&J, 0, sizeof J);
+    J.n = n; J.cplx = 0; J.a = NULL;
+    J.csc_ptr = col_ptr; J.csc_row = row_idx; J.csc_val = vals;
+    J.x0r = x0r; J.x0i = x0i;
+    double tmp[4];
+    int rc = walk_all(&J, nthreads, tmp, absum);
+    if (rc == 0) { out[0] = tmp[0]; out[1] = tmp[1]; }
+    return rc;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -17,7 +17,7 @@ def test_sparse_uniform_values(oracle, n, per_row):
     want = oracle.ryser(a)
     assert abs(got - want) <= 1e-10 * abs(want), (got, want)
     if n <= 22:
-        assert abs(oracle.sparyser(a) - want) <= 1e-12 * abs(want)
+        assert abs(oracle.sparse(a) - want) <= 1e-12 * abs(want)
 
 
 def test_sparse_signed_values(oracle):

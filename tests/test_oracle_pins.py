@@ -175,19 +175,99 @@ def test_complex_phase_construction(oracle):
     assert abs(oracle.ryser(c) - want) < 1e-14 * abs(want)
 
 
-def test_sparyser_matches_ryser(oracle):
-    a = W.sparse_rows(16, 4, 3).astype(np.float64) * W.uniform(16, 4)
-    assert rel(oracle.sparyser(a), oracle.ryser(a)) < 1e-13
+# --- Algorithm 2 on CSC columns -----------------------------------------------
+
+def test_csc_walk_equals_dense_walk(oracle):
+    # a step adds only the flipped column's nonzeros; adding the zeros as
+    # well (the dense walk) changes no value, so the two agree bit for bit
+    for n, per_row, seed in ((9, 3, 1), (16, 4, 3), (21, 5, 4)):
+        a = W.sparse_rows(n, per_row, seed).astype(np.float64) * W.uniform(n, seed + 10)
+        a[0, :] *= -1.0  # signed entries too
+        assert oracle.sparse(a) == oracle.ryser(a)
 
 
-def test_absolute_sum_bounds_value(oracle):
-    a = W.rademacher(14, 11)
+def test_csc_walk_closed_forms(oracle):
+    for n in (1, 2, 7, 13, 18):
+        assert oracle.sparse(np.eye(n)) == 1.0
+        assert rel(oracle.sparse(W.ones_minus_identity(n)), derangements(n)) < 1e-14
+        assert rel(oracle.sparse(W.tridiagonal_ones(n)), fib(n + 1)) < 1e-14
+        assert rel(oracle.sparse(W.block_ones(n, 3)), (
+            math.factorial(3) ** (n // 3) * math.factorial(n % 3))) < 1e-14
+
+
+# --- R(A), the Ryser absolute sum 2 sum_g |prod_i x_i(g)| ---------------------
+# Closed forms that follow from Algorithm 1's start vector
+# x_i(S) = a_{i,n-1} + sum_{j in S} a_ij - r_i / 2 over the subsets S of the
+# first n - 1 columns:
+#   * I_n: every x_i(S) is +-1/2, so each of the 2^(n-1) terms is 2^-n: R = 1.
+#   * diag(d): x_i(S) = +-d_i / 2, so R = prod_i |d_i| (also for complex d).
+#   * J_n: x_i(S) = |S| + 1 - n/2 in every row, so
+#     R = 2 sum_k C(n-1, k) |k + 1 - n/2|^n.
+#   * scaling row i by c multiplies every x_i(S) by c: R(DA) = prod|d_i| R(A).
+
+def r_all_ones(n):
+    from fractions import Fraction
+    tot = sum(math.comb(n - 1, k) * abs(Fraction(2 * (k + 1) - n, 2)) ** n for k in range(n))
+    return float(2 * tot)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 8, 13, 20])
+def test_r_identity_is_one(oracle, n):
+    _, r = oracle.ryser(np.eye(n), with_abs=True)
+    assert r == 1.0
+
+
+@pytest.mark.parametrize("n", [2, 5, 11, 17])
+def test_r_diagonal(oracle, n):
+    rng = np.random.default_rng(40 + n)
+    d = rng.random(n) + 0.25
+    d[rng.random(n) < 0.5] *= -1.0
+    _, r = oracle.ryser(np.diag(d), with_abs=True)
+    assert rel(r, float(np.prod(np.abs(d)))) < 1e-14
+    # complex diagonal: the modulus of each complex term
+    z = d * np.exp(1j * rng.random(n) * 2 * np.pi)
+    _, rc = oracle.ryser(np.diag(z), with_abs=True)
+    assert rel(rc, float(np.prod(np.abs(z)))) < 1e-14
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 6, 9, 14, 19])
+def test_r_all_ones_closed_form(oracle, n):
+    _, r = oracle.ryser(W.all_ones(n), with_abs=True)
+    assert rel(r, r_all_ones(n)) < 1e-14
+    # all entries 0.91: every x_i(S) scales by 0.91
+    _, r91 = oracle.ryser(np.full((n, n), 0.91), with_abs=True)
+    assert rel(r91, r_all_ones(n) * 0.91 ** n) < 1e-13
+
+
+def test_r_brute_force_subsets(oracle):
+    # tiny orders: the absolute subset sum term by term, without the Gray order
+    rng = np.random.default_rng(17)
+    for n in range(1, 9):
+        for a in (rng.standard_normal((n, n)),
+                  rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))):
+            x0 = a[:, n - 1] - a.sum(axis=1) / 2
+            tot = 0.0
+            for s in range(2 ** (n - 1)):
+                cols = [j for j in range(n - 1) if (s >> j) & 1]
+                tot += abs(np.prod(x0 + a[:, cols].sum(axis=1)))
+            _, r = oracle.ryser(a, with_abs=True)
+            assert rel(r, 2 * tot) < 1e-13, n
+
+
+def test_r_invariances(oracle):
+    rng = np.random.default_rng(18)
+    n = 12
+    a = rng.standard_normal((n, n))
     v, r = oracle.ryser(a, with_abs=True)
     assert abs(v) <= r
-    # for a nonnegative matrix with all x_i > 0 only for S = all columns the
-    # bound is loose, but R(A) >= |perm| always and R(J) >= n!
-    v, r = oracle.ryser(W.all_ones(10), with_abs=True)
-    assert r >= math.factorial(10)
+    pr = rng.permutation(n)                       # rows: the x_i are permuted
+    assert rel(oracle.ryser(a[pr], with_abs=True)[1], r) < 1e-14
+    pc = np.concatenate([rng.permutation(n - 1), [n - 1]])  # columns other than the last
+    assert rel(oracle.ryser(a[:, pc], with_abs=True)[1], r) < 1e-14
+    d = rng.random(n) + 0.5
+    assert rel(oracle.ryser(d[:, None] * a, with_abs=True)[1], float(np.prod(d)) * r) < 1e-13
+    c = a * np.exp(1j * rng.random(n) * 2 * np.pi)[:, None]  # unit phases on the rows
+    assert rel(oracle.ryser(c, with_abs=True)[1], r) < 1e-13
 
 
 # --- exact binary ------------------------------------------------------------
@@ -270,12 +350,24 @@ def _pins_pass(orc: Oracle) -> bool:
         a = W.bernoulli(9, 5)
         if orc.binary(a) != orc.matchings(a):
             return False
+        # R(A) closed forms
+        if orc.ryser(np.eye(6), with_abs=True)[1] != 1.0:
+            return False
+        z = np.array([0.5, 1.5, 2.0, 0.75]) * np.exp(1j * np.array([0.3, 1.1, 2.0, 4.0]))
+        if abs(orc.ryser(np.diag(z), with_abs=True)[1] - np.prod(np.abs(z))) > 1e-14:
+            return False
+        # Algorithm 2 on CSC columns
+        if round(orc.sparse(W.ones_minus_identity(6))) != 265:
+            return False
+        s = W.sparse_rows(8, 3, 2).astype(np.float64) * W.uniform(8, 3)
+        if orc.sparse(s) != orc.ryser(s):
+            return False
         return True
     except RuntimeError:
         return False
 
 
-@pytest.mark.parametrize("mutant", [1, 2, 3, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("mutant", [1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11])
 def test_mutants_are_caught(mutant):
     with tempfile.TemporaryDirectory() as td:
         path = os.path.join(td, f"liboracle_m{mutant}.so")
