@@ -10,15 +10,26 @@ column subsets, and the fixed-order reduction -- so one step processes
 
 roofline: the sweep is bound by the FP64 vector ALU.  Algorithmic work per
 subset-step is 2n + 2 flops (n additions, n multiplications, the sign and
-the accumulation; the count the paper uses for its error estimate).  None of
-it is multiply-add shaped, so one FP64 lane-operation per flop: the ceiling
-is 256 CUs x 64 FP64 lanes/clock x 2.4 GHz = 39.32 Tflop/s (the published
-78.6 TFLOP/s counts an FMA as two flops).  The duration is the average HIP
-event time of one call on the launch stream, which includes the two tiny
-kernels around the sweep (under 0.5 % of it).
+the accumulation; the count the paper uses for its error estimate).  `peak`
+is the published FP64 vector peak, 78.6 TFLOP/s, which counts a multiply-add
+as two flops; none of this loop's work is multiply-add shaped, so `frac`
+cannot exceed 0.5.  `issue_slot_utilisation` is the same work counted as
+FP64 lane-operations (one add or multiply each) over the issue rate of
+256 CUs x 64 lanes x 2.4 GHz = 3.93e13 per second, whose ceiling is 1.  The
+duration is the average HIP event time of one call on the launch stream,
+which includes the two tiny kernels around the sweep (under 0.5 % of it).
 
-cpu_baseline: the CPU oracle (long double, all host threads) timed on a
-bounded sample of the same matrix's Gray walk, scaled to subset-steps/s.
+rows: the other hot-path rows measured in the same run (complex 30 x 30,
+exact binary 32 x 32 and 40 x 40, sparse real 40 x 40, perm + gradient of a
+24 x 24 matrix), each with its time and its difference from the stored
+oracle value (tests/golden/) against the tolerance used in the tests.
+
+batched: one hipGraph launch of perm + dperm/dA for the 4096-matrix batch,
+against per-matrix launches captured in graphs (so the device time is
+compared, not the Python launch loop), with the accuracy of both checked.
+
+cpu_baseline: the CPU oracle (long double) timed on a bounded sample of the
+same matrix's Gray walk, on the cores this process may use.
 """
 from __future__ import annotations
 
@@ -32,8 +43,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 N = 32
-PEAK_ALU_TFLOPS = 256 * 64 * 2.4e9 / 1e12      # 39.32: one add or mul per lane per clock
-PEAK_FMA_TFLOPS = 78.6                           # published FP64 vector peak (FMA = 2 flops)
+PEAK_FP64_TFLOPS = 78.6                          # published FP64 vector peak (FMA = 2 flops)
+LANE_OPS_PER_S = 256 * 64 * 2.4e9                # FP64 lane-operations issued per second
+GOLDEN = os.path.join(ROOT, "tests", "golden")
 
 # HBM bytes per sweep launch from rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by a
 # plain 1 GiB copy (profiles/sweep_dense_f64_n32_u01.md).  Valid only for the
@@ -50,11 +62,46 @@ def traffic_bytes():
     return TRAFFIC_BYTES_PER_LAUNCH if ok else None
 
 
+def _golden(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+def host_cpu():
+    """Cores this process may use: its affinity set, capped by the cgroup CPU
+    quota where one is set; with nproc and the CPU model."""
+    nproc = os.cpu_count() or 1
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = nproc
+    quota = None
+    try:
+        with open("/sys/fs/cgroup/cpu.max") as f:
+            q, per = f.read().split()[:2]
+            if q != "max":
+                quota = max(1, int(int(q) / int(per)))
+    except (OSError, ValueError):
+        pass
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    threads = min(affinity, quota) if quota else affinity
+    return {"threads": threads, "nproc": nproc, "affinity": affinity, "cgroup_quota_cpus": quota,
+            "cpu_model": model}
+
+
 def cpu_baseline(a, target_seconds=12.0):
     from oracle.oracle import default
     orc = default()
-    # the host's share of cores: OMP_NUM_THREADS where set, at most 16
-    threads = min(int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1), 16)
+    cpu = host_cpu()
+    threads = cpu["threads"]
     chunk = orc.CHUNK_STEPS
     nch = 256
     t0 = time.perf_counter()
@@ -75,17 +122,43 @@ def cpu_baseline(a, target_seconds=12.0):
     return {"value": steps / dt, "unit": "subset-steps/s", "cores": threads, "kind": "oracle",
             "sample": f"{steps} of the 2^31 Gray steps of the same 32x32 U[0,1) matrix "
                       f"({nch} chunks of {chunk} steps, long double), {dt:.2f} s wall",
+            "host": cpu,
             "single_thread": {"value": n1 * chunk / dt1, "unit": "subset-steps/s",
                               "sample": f"{n1} chunks of {chunk} steps on one thread, "
                                         f"{dt1:.2f} s wall"}}
 
 
+def _graph_ms(fn, reps=3):
+    """Captures the launches fn() makes on the current stream into one graph,
+    replays it (once untimed) and returns the average HIP-event milliseconds
+    of a replay: the device time of the launches without the host's Python
+    loop between them."""
+    import torch
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        fn()
+    g.replay()
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        g.replay()
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del g
+    return ms
+
+
 def bench_batched(reps: int = 5, use_graph: bool = True, baselines: bool = True):
     """Batched perm + dperm/dA of the 4096-matrix photon-counting batch (one
-    hipGraph launch) against per-matrix launches: of perm_grad, and of the
-    plain forward solver (perm_dense_c128 on the matrix and on each of its
-    k^2 minors), the latter timed on one matrix per order and extrapolated
-    over the batch's order histogram."""
+    hipGraph launch) against per-matrix launches, each side's device time:
+    perm_grad on every matrix (all 4096 calls captured in one graph), and the
+    plain forward solver -- perm_dense_c128 on the matrix and on each of its
+    k^2 minors -- captured per order for one matrix of every order and scaled
+    by the batch's order histogram.  Accuracy: the batch against the stored
+    oracle sample, and every per-matrix result against the batch."""
     import numpy as np
     import torch
     from paper_2502_16577_amd import api, workloads
@@ -95,88 +168,118 @@ def bench_batched(reps: int = 5, use_graph: bool = True, baselines: bool = True)
     ks, offs, data = workloads.pack(mats)
     d = torch.from_numpy(data).to(dev)
     plan = api.BatchedPlan(ks, offs, want_grad=True)
-    tuned_ms = plan.autotune(d)
-    out, grad = plan.outputs(d)
-    stream = torch.cuda.current_stream(dev)
-    for _ in range(2):
-        plan.run(d, out=out, grad=grad, use_graph=use_graph)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(reps):
-        plan.run(d, out=out, grad=grad, use_graph=use_graph)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    batch_ms = e0.elapsed_time(e1) / reps
+    try:
+        tuned_ms = plan.autotune(d)
+        out, grad = plan.outputs(d)
+        stream = torch.cuda.current_stream(dev)
+        for _ in range(2):
+            plan.run(d, out=out, grad=grad, use_graph=use_graph)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            plan.run(d, out=out, grad=grad, use_graph=use_graph)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        batch_ms = e0.elapsed_time(e1) / reps
+        info = plan.info()
+    finally:
+        plan.close()
+    rec = {"workload": "4096 complex128 k x k submatrices, k ~ U{8..24}, rows/cols drawn with "
+                       "repetition from a 64x64 Haar unitary (seeds 16583, 16584); perm + dperm/dA",
+           "matrices": 4096, "subset_steps": int(sum(2 ** (int(k) - 1) for k in ks)),
+           "batch_ms": batch_ms, "value": 4096 / (batch_ms * 1e-3),
+           "unit": "matrices/s (perm+grad)", "graph": use_graph,
+           "autotuned": {"best_ms": tuned_ms, **info}}
+    # FP64 slot operations of the complex sweep with its gradient, 20k + 60
+    # per subset-step (as for the single-matrix adjoint)
+    alu_ops = float(sum((2 ** (int(k) - 1)) * (20 * int(k) + 60) for k in ks))
+    lane_ops_per_s = alu_ops / (batch_ms * 1e-3)
+    rec["roofline"] = {"bound": "alu", "achieved": lane_ops_per_s / 1e12, "peak": LANE_OPS_PER_S / 1e12,
+                       "unit": "T lane-ops/s", "frac": lane_ops_per_s / LANE_OPS_PER_S,
+                       "ops_per_subset_step": "20k + 60",
+                       "note": "FP64 lane-operations (add, mul, FMA one each) over the issue "
+                               "rate 256 x 64 x 2.4e9"}
     if not baselines:
-        return {"matrices": 4096, "batch_ms": batch_ms, "value": 4096 / (batch_ms * 1e-3),
-                "unit": "matrices/s (perm+grad)", "graph": use_graph,
-                "autotuned": {"best_ms": tuned_ms, **plan.info()}}
+        return rec
 
-    # per-matrix perm_grad launches over the whole batch
+    oh = out.cpu().numpy()
+    gh = grad.cpu().numpy()
+    G = [gh[o:o + k * k].reshape(k, k) for k, o in zip(ks, offs)]
+    # accuracy of the batch against the stored oracle sample
+    smp = _golden("samples.json")["batched"]
+    assert smp["digest"] == workloads.digest(data), "batched sample input drifted"
+    worst = {"perm": 0.0, "minor": 0.0, "fd": 0.0}
+    for e in smp["perms"]:
+        want = complex(*e["value"])
+        worst["perm"] = max(worst["perm"], abs(oh[e["m"]] - want) / (1e-13 * e["abs_sum"]))
+    for e in smp["minors"]:
+        want = complex(*e["value"])
+        worst["minor"] = max(worst["minor"], abs(G[e["m"]][e["i"], e["j"]] - want) / (1e-10 * e["abs_perm"]))
+    for e in smp["fd"]:
+        want = complex(*e["value"])
+        worst["fd"] = max(worst["fd"], abs(G[e["m"]][e["i"], e["j"]] - want) / (1e-6 * abs(want)))
+    rec["accuracy_vs_oracle"] = {
+        "sample": f"{len(smp['perms'])} permanents, {len(smp['minors'])} minors, "
+                  f"{len(smp['fd'])} central differences (tests/golden/samples.json)",
+        "worst_over_tolerance": worst,
+        "tolerances": "perm 1e-13 R(A); minor 1e-10 perm(|minor|); FD 1e-6 |FD|"}
+
+    # per-matrix perm_grad: every call captured into one graph
     dm = [torch.from_numpy(a).to(dev) for a in mats]
     wsg = torch.empty(max(api.workspace_bytes(6, n) for n in range(1, 25)), dtype=torch.uint8,
                       device=dev)
-    po = torch.empty((), dtype=torch.complex128, device=dev)
-    go = torch.empty((24, 24), dtype=torch.complex128, device=dev)
-    for a in dm[:64]:
-        k = a.shape[0]
-        api.perm_grad(a, out_perm=po, out_grad=go[:k, :k].contiguous(), ws=wsg)
-    torch.cuda.synchronize()
+    pbuf = torch.empty(4096, dtype=torch.complex128, device=dev)
     gbuf = [torch.empty((a.shape[0], a.shape[0]), dtype=torch.complex128, device=dev) for a in dm]
-    t0 = time.perf_counter()
-    for a, g in zip(dm, gbuf):
-        api.perm_grad(a, out_perm=po, out_grad=g, ws=wsg)
-    torch.cuda.synchronize()
-    per_grad_ms = (time.perf_counter() - t0) * 1e3
 
-    # plain forward solver: perm + every minor, one launch each (sampled per order)
+    def per_matrix():
+        for m, (a, g) in enumerate(zip(dm, gbuf)):
+            api.perm_grad(a, out_perm=pbuf[m], out_grad=g, ws=wsg)
+
+    t0 = time.perf_counter()
+    per_matrix()
+    torch.cuda.synchronize()
+    per_wall_ms = (time.perf_counter() - t0) * 1e3
+    per_grad_ms = _graph_ms(per_matrix)
+    pb = pbuf.cpu().numpy()
+    diff_p = max(abs(pb[m] - oh[m]) / max(abs(oh[m]), 1e-300) for m in range(4096))
+    diff_g = max(float(np.max(np.abs(gbuf[m].cpu().numpy() - G[m])) / np.max(np.abs(G[m])))
+                 for m in range(4096))
+
+    # plain forward solver: perm + every minor, 1 + k^2 launches per matrix,
+    # captured per order for one matrix of that order
     wsp = torch.empty(max(api.workspace_bytes(2, n) for n in range(1, 25)), dtype=torch.uint8,
                       device=dev)
-    per_k = {}
+    per_k, plain_diff = {}, 0.0
     for k in sorted(set(int(x) for x in ks)):
         m = int(np.nonzero(ks == k)[0][0])
         a = mats[m]
         minors = [torch.from_numpy(np.ascontiguousarray(np.delete(np.delete(a, i, 0), j, 1))).to(dev)
                   for i in range(k) for j in range(k)]
-        full = dm[m]
-        api.perm_dense_c128(full, out=po, ws=wsp)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        api.perm_dense_c128(full, out=po, ws=wsp)
-        for mm in minors:
-            api.perm_dense_c128(mm, out=po, ws=wsp)
-        torch.cuda.synchronize()
-        per_k[k] = (time.perf_counter() - t0) * 1e3
-    plain_ms = float(sum(per_k[int(k)] for k in ks))
+        res = torch.empty(1 + k * k, dtype=torch.complex128, device=dev)
 
-    # GEMM-equivalent work of the contraction G += V tau^T: 2 real GEMMs (Re, Im
-    # of V) x 2 k^2 flops per subset; the windowed kernel issues 1/16 of it on MFMA
-    mfma_flops = float(sum((2 ** (int(k) - 1)) * 4 * int(k) ** 2 for k in ks))
-    # FP64 slot operations of the complex sweep with its gradient, 20k + 60
-    # per subset-step (as for the single-matrix adjoint)
-    alu_ops = float(sum((2 ** (int(k) - 1)) * (20 * int(k) + 60) for k in ks))
-    alu_tflops = alu_ops / (batch_ms * 1e-3) / 1e12
-    return {
-        "workload": "4096 complex128 k x k submatrices, k ~ U{8..24}, rows/cols drawn with "
-                    "repetition from a 64x64 Haar unitary (seeds 16583, 16584); perm + dperm/dA",
-        "matrices": 4096,
-        "subset_steps": int(sum(2 ** (int(k) - 1) for k in ks)),
-        "batch_ms": batch_ms,
-        "value": 4096 / (batch_ms * 1e-3),
-        "unit": "matrices/s (perm+grad)",
-        "autotuned": {"best_ms": tuned_ms, **plan.info()},
+        def plain():
+            api.perm_dense_c128(dm[m], out=res[0], ws=wsp)
+            for t, mm in enumerate(minors):
+                api.perm_dense_c128(mm, out=res[1 + t], ws=wsp)
+
+        per_k[k] = _graph_ms(plain, reps=1)
+        rh = res.cpu().numpy()
+        plain_diff = max(plain_diff, float(np.max(np.abs(rh[1:].reshape(k, k) - G[m])) / np.max(np.abs(G[m]))))
+    plain_ms = float(sum(per_k[int(k)] for k in ks))
+    rec.update({
         "per_matrix_perm_grad_ms": per_grad_ms,
+        "per_matrix_perm_grad_python_loop_ms": per_wall_ms,
+        "speedup_vs_per_matrix_perm_grad": per_grad_ms / batch_ms,
+        "per_matrix_vs_batch_max_rel_diff": {"perm": diff_p, "grad": diff_g},
         "plain_solver_ms_extrapolated": plain_ms,
         "plain_solver_sample": "one matrix per order k: perm_dense_c128 on A and on each of its "
-                               "k^2 minors (1 + k^2 launches), scaled by the order histogram",
+                               "k^2 minors (1 + k^2 launches, one graph per order), scaled by the "
+                               "order histogram",
+        "plain_solver_vs_batch_max_rel_diff_grad": plain_diff,
         "speedup_vs_plain_solver": plain_ms / batch_ms,
-        "speedup_vs_per_matrix_perm_grad": per_grad_ms / batch_ms,
-        "gemm_equivalent_tflops": mfma_flops / (batch_ms * 1e-3) / 1e12,
-        "roofline": {"bound": "alu", "achieved": alu_tflops, "peak": PEAK_ALU_TFLOPS,
-                     "unit": "TFLOP/s", "frac": alu_tflops / PEAK_ALU_TFLOPS,
-                     "ops_per_subset_step": "20k + 60"},
-    }
+    })
+    return rec
 
 
 def _timed(fn, reps, stream):
@@ -191,144 +294,150 @@ def _timed(fn, reps, stream):
     return e0.elapsed_time(e1) / reps
 
 
-def bench_rows():
-    """One JSON line per hot-path row other than the headline: the complex
-    sweep (30x30 Haar block), the sparse real path and the Section 4 pipeline
-    (40x40, 6 per row), the exact binary path (32x32 Bernoulli, 40x40 sparse),
-    and perm + dperm/dA of one matrix (24x24 real and complex)."""
+def measure_rows():
+    """The hot-path rows other than the headline, each timed and checked
+    against the stored oracle value: the complex sweep (30x30 Haar block),
+    the exact binary path (32x32 Bernoulli; the 40x40 sparse pattern, staged
+    and generated kernels), the sparse real path (the 40x40 pattern), and
+    perm + dperm/dA of one 24x24 matrix (complex and real).  Returns
+    {name: record}."""
+    import numpy as np
     import torch
     from paper_2502_16577_amd import api, workloads
 
     dev = torch.device("cuda:0")
     st = torch.cuda.current_stream(dev)
+    full = _golden("full_size.json")
+    smp = _golden("samples.json")
+    rows = {}
 
-    def line(rec):
-        print(json.dumps(rec), flush=True)
-
-    # a7: complex dense sweep, priced like the real one in FP64 operations
-    # that each take one instruction slot (add, mul, FMA): 2n adds, n - 1
-    # complex products of 2 mul + 2 FMA, 2 accumulation adds = 6n - 2 per step
+    # a7: complex dense sweep.  FP64 lane-operations per subset-step: 2n
+    # adds, n - 1 complex products of 2 mul + 2 FMA, 2 accumulation adds
     n = 30
-    A = torch.from_numpy(workloads.haar_block(120, n, workloads.SEED_HAAR120)).to(dev)
+    a = workloads.haar_block(120, n, workloads.SEED_HAAR120)
+    g = full["haar30"]
+    assert workloads.digest(a) == g["digest"]
+    A = torch.from_numpy(a).to(dev)
     out = torch.empty((), dtype=torch.complex128, device=dev)
     ws = torch.empty(api.workspace_bytes(2, n), dtype=torch.uint8, device=dev)
     for _ in range(10):  # untimed: the first calls run while the clocks ramp up
         api.perm_dense_c128(A, out=out, ws=ws)
     ms = _timed(lambda: api.perm_dense_c128(A, out=out, ws=ws), 10, st)
-    fl = (6 * n - 2) * 2 ** (n - 1)
-    line({"row": "a7 complex sweep", "workload": "30x30 block of a 120x120 Haar unitary (seed 16581)",
-          "ms": ms, "subset_steps_per_s": 2 ** (n - 1) / (ms * 1e-3),
-          "roofline": {"bound": "alu", "achieved": fl / (ms * 1e-3) / 1e12, "peak": PEAK_ALU_TFLOPS,
-                       "unit": "TFLOP/s", "frac": fl / (ms * 1e-3) / 1e12 / PEAK_ALU_TFLOPS,
-                       "ops_per_subset_step": 6 * n - 2,
-                       "flops_per_subset_step_fma_as_2": 8 * n - 4}})
+    want = complex(sum(g["re"]), sum(g["im"]))
+    err = abs(complex(out.item()) - want)
+    ops = (6 * n - 2) * 2 ** (n - 1)
+    rows["a7_complex30"] = {
+        "workload": "30x30 block of a 120x120 Haar unitary (seed 16581)", "ms": ms,
+        "subset_steps_per_s": 2 ** (n - 1) / (ms * 1e-3),
+        "issue_slot_utilisation": ops / (ms * 1e-3) / LANE_OPS_PER_S,
+        "abs_err": err, "tol": min(1e-13 * g["abs_sum"], 1e-10 * g["abs_perm"]),
+        "ok": err <= 1e-13 * g["abs_sum"] and err <= 1e-10 * g["abs_perm"]}
 
-    # a8: sparse real (staged columns) and the Section 4 decomposition path
+    # a9: exact binary, 32x32 Bernoulli and the 40x40 sparse pattern
+    for name, key, a01 in (("a9_binary32", "bernoulli32", workloads.bernoulli(32, workloads.SEED_BERNOULLI32)),
+                           ("a9_binary40", "sparse40", workloads.sparse_rows(40, 6, workloads.SEED_SPARSE40))):
+        g = full[key]
+        assert workloads.digest(a01) == g["digest"]
+        rec = {"workload": {"bernoulli32": "32x32 Bernoulli(1/2) (seed 16580)",
+                            "sparse40": "40x40 0/1, 6 per row (seed 16582)"}[key]}
+        for label, gen in (("staged", False), ("generated", True)):
+            t0 = time.perf_counter()
+            api.perm_binary_exact(a01, generated=gen)  # the generated path compiles here
+            first = time.perf_counter() - t0
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            t0 = time.perf_counter()
+            e0.record(st)
+            val, res = api.perm_binary_exact(a01, generated=gen)
+            e1.record(st)
+            dt = time.perf_counter() - t0
+            torch.cuda.synchronize()
+            rec[label] = {"seconds": dt, "gpu_seconds": e0.elapsed_time(e1) * 1e-3,
+                          "first_call_seconds": first, "exact": str(val) == g["value"]}
+        rows[name] = rec
+
+    # a8: sparse real, the 40x40 pattern with U[0,1) values (stored oracle
+    # value of Algorithm 2's CSC walk), else with its 0/1 values (exact)
+    n = 40
+    pat = workloads.sparse_rows(n, 6, workloads.SEED_SPARSE40)
+    if "sparse40u" in full:
+        a = pat * workloads.uniform(n, workloads.SEED_SPARSE40_VALUES)
+        g = full["sparse40u"]
+        values = "U[0,1) (seed 16585)"
+    else:
+        a = pat.astype(np.float64)
+        g = {"digest": workloads.digest(pat), "value": [float(full["sparse40"]["value"]), 0.0]}
+        values = "1 (the 0/1 pattern as reals)"
+    assert workloads.digest(a if "sparse40u" in full else pat) == g["digest"]
+    cp, ri, va = workloads.to_csc(a)
+    out = torch.empty((), dtype=torch.float64, device=dev)
+    wss = torch.empty(api.workspace_bytes(3, n, len(ri)), dtype=torch.uint8, device=dev)
+    t0 = time.perf_counter()
+    api.perm_sparse_f64(n, cp, ri, va, out=out, ws=wss)
+    torch.cuda.synchronize()
+    first = time.perf_counter() - t0
+    ms = _timed(lambda: api.perm_sparse_f64(n, cp, ri, va, out=out, ws=wss), 3, st)
+    want = sum(g["value"])
+    rel = abs(out.item() - want) / abs(want)
+    ms_staged = _timed(lambda: api.perm_sparse_f64_staged(n, cp, ri, va, out=out, ws=wss), 1, st)
+    rel_staged = abs(out.item() - want) / abs(want)
+    rows["a8_sparse40"] = {
+        "workload": f"40x40 pattern with 6 per row (seed 16582), values {values}; "
+                    "perm_sparse_f64 (kernel generated for the pattern)",
+        "ms": ms, "first_call_seconds": first, "subset_steps_per_s": 2 ** (n - 1) / (ms * 1e-3),
+        "rel_err": rel, "tol": 1e-10, "ok": rel <= 1e-10,
+        "staged_ms": ms_staged, "staged_rel_err": rel_staged}
+
+    # a10: perm + dperm/dA of one 24x24 matrix (complex and real)
+    for name, key, mat in (("a10_grad24c", "grad24c", workloads.haar_block(120, 24, workloads.SEED_HAAR120)),
+                           ("a10_grad24r", "grad24r", workloads.uniform(24, 1024))):
+        n = 24
+        g = smp[key]
+        assert workloads.digest(mat) == g["digest"]
+        A = torch.from_numpy(mat).to(dev)
+        po = torch.empty((), dtype=A.dtype, device=dev)
+        go = torch.empty((n, n), dtype=A.dtype, device=dev)
+        cplx = key.endswith("c")
+        wsg = torch.empty(api.workspace_bytes(6 if cplx else 5, n), dtype=torch.uint8, device=dev)
+        for _ in range(3):
+            api.perm_grad(A, out_perm=po, out_grad=go, ws=wsg)
+        ms = _timed(lambda: api.perm_grad(A, out_perm=po, out_grad=go, ws=wsg), 5, st)
+        pv = complex(po.item())
+        gh = go.cpu().numpy()
+        perr = abs(pv - complex(*g["perm"])) / (1e-13 * g["abs_sum"])
+        merr = max(abs(gh[e["i"], e["j"]] - complex(*e["value"])) / (1e-10 * e["abs_perm"])
+                   for e in g["minors"])
+        # FP64 lane-operations per subset-step as designed: x update, forward
+        # product, three products per row for the leave-one-out products, the
+        # window sums of V and the 16-lane partial sums for the low columns
+        ops = (20 * n + 60) if cplx else (6 * n + 31)
+        rows[name] = {"workload": f"24x24 {'Haar block (seed 16581)' if cplx else 'U[0,1) (seed 1024)'}",
+                      "ms": ms, "subset_steps_per_s": 2 ** (n - 1) / (ms * 1e-3),
+                      "issue_slot_utilisation": ops * 2 ** (n - 1) / (ms * 1e-3) / LANE_OPS_PER_S,
+                      "perm_err_over_tol": perr, "minor_err_over_tol": merr,
+                      "tol": "perm 1e-13 R(A); minors 1e-10 perm(|minor|)",
+                      "ok": perr <= 1.0 and merr <= 1.0}
+    return rows
+
+
+def bench_rows():
+    """One JSON line per hot-path row other than the headline (measure_rows),
+    and the Section 4 pipeline on the 40x40 sparse matrix."""
+    import torch
+    from paper_2502_16577_amd import api, workloads
+
+    for name, rec in measure_rows().items():
+        print(json.dumps({"row": name, **rec}), flush=True)
     n = 40
     a = workloads.sparse_rows(n, 6, workloads.SEED_SPARSE40)
     cp, ri, va = workloads.to_csc(a)
-    api.perm_sparse_f64(n, cp, ri, va)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    v = api.perm_sparse_f64(n, cp, ri, va).item()
-    dt = time.perf_counter() - t0
-    nnz_col = len(ri) / n
-    fl = (n - 1 + nnz_col + 1) * 2 ** (n - 1)  # products, the column's nonzeros, accumulation
-    line({"row": "a8 sparse real", "workload": "40x40 0/1 as f64, 6 per row (seed 16582)",
-          "seconds": dt, "perm": v, "subset_steps_per_s": 2 ** (n - 1) / dt,
-          "roofline": {"bound": "alu", "achieved": fl / dt / 1e12, "peak": PEAK_ALU_TFLOPS,
-                       "unit": "TFLOP/s", "frac": fl / dt / 1e12 / PEAK_ALU_TFLOPS,
-                       "flops_per_subset_step": n - 1 + nnz_col + 1,
-                       "note": "staged dense columns: n adds per step are executed"}})
-    # the same matrix through the kernel generated for its pattern (the first
-    # call compiles it; the timed call reuses the cached module)
-    t0 = time.perf_counter()
-    api.perm_sparse_f64_gen(n, cp, ri, va)
-    torch.cuda.synchronize()
-    first = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    v = api.perm_sparse_f64_gen(n, cp, ri, va).item()
-    dt = time.perf_counter() - t0
-    # (no roofline: inside a 16-step block the generated product re-uses the
-    # product of the rows the block does not touch, so it executes far fewer
-    # operations than the n - 1 + nnz_j per step the method is priced at)
-    line({"row": "next-4 generated sparse kernel", "workload": "same 40x40 matrix, kernel "
-          "generated for its pattern (hiprtc)", "seconds": dt, "first_call_seconds": first,
-          "perm": v, "subset_steps_per_s": 2 ** (n - 1) / dt,
-          "method_flops_per_s": fl / dt})
     api.perm_sparse_decomp(n, cp, ri, va)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     v = api.perm_sparse_decomp(n, cp, ri, va).item()
     dt = time.perf_counter() - t0
-    line({"row": "next-3 DecompRyser", "workload": "same 40x40 matrix, DM pruning + Forbert-Marx, "
-          "leaves batched on the GPU (host decomposition included)", "seconds": dt, "perm": v})
-
-    # a9: exact binary
-    for name, a01 in (("32x32 Bernoulli(1/2) (seed 16580)",
-                       workloads.bernoulli(32, workloads.SEED_BERNOULLI32)),
-                      ("40x40 0/1, 6 per row (seed 16582)", a)):
-        nb = a01.shape[0]
-        api.perm_binary_exact(a01)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        t0 = time.perf_counter()
-        e0.record(st)
-        val, res = api.perm_binary_exact(a01)
-        e1.record(st)
-        dt = time.perf_counter() - t0
-        torch.cuda.synchronize()
-        gpu_s = e0.elapsed_time(e1) * 1e-3  # staging copy + kernels, on the call's stream
-        rec = {"row": "a9 binary exact", "workload": name, "seconds": dt, "gpu_seconds": gpu_s,
-               "perm": str(val), "primes": len(res), "subset_steps_per_s": 2 ** (nb - 1) / dt}
-        if nb == 32:
-            # every subset-step of a dense pattern costs the n adds and n - 1
-            # multiplies of the exact FP64 products (plus the zero test), the
-            # same FP64 slot count as the real sweep; the modular products of
-            # the 9 % nonzero terms come on top
-            ops = 2 * nb * 2 ** (nb - 1)
-            rec["roofline"] = {"bound": "alu", "achieved": ops / gpu_s / 1e12,
-                               "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s",
-                               "frac": ops / gpu_s / 1e12 / PEAK_ALU_TFLOPS,
-                               "ops_per_subset_step": 2 * nb}
-        line(rec)
-        # the same through the kernel generated for the pattern
-        t0 = time.perf_counter()
-        api.perm_binary_exact(a01, generated=True)
-        first = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        gval, gres = api.perm_binary_exact(a01, generated=True)
-        dt = time.perf_counter() - t0
-        line({"row": "a9 binary exact, generated kernel", "workload": name, "seconds": dt,
-              "first_call_seconds": first, "perm": str(gval), "equal": gval == val,
-              "subset_steps_per_s": 2 ** (nb - 1) / dt})
-
-    # a10: perm + dperm/dA of one matrix
-    for dtype, mat in (("f64", workloads.uniform(24, 1024)),
-                       ("c128", workloads.haar_block(120, 24, workloads.SEED_HAAR120))):
-        n = 24
-        A = torch.from_numpy(mat).to(dev)
-        po = torch.empty((), dtype=A.dtype, device=dev)
-        go = torch.empty((n, n), dtype=A.dtype, device=dev)
-        kind = 5 if dtype == "f64" else 6
-        wsg = torch.empty(api.workspace_bytes(kind, n), dtype=torch.uint8, device=dev)
-        api.perm_grad(A, out_perm=po, out_grad=go, ws=wsg)
-        ms = _timed(lambda: api.perm_grad(A, out_perm=po, out_grad=go, ws=wsg), 5, st)
-        cplx = dtype == "c128"
-        # G = sum over subsets of V tau^T: n^2 multiply-adds per subset (x2 for complex V)
-        gemm = (4 if cplx else 2) * n * n * 2 ** (n - 1)
-        # FP64 slot operations per subset-step of the sweep as designed: the x
-        # update, the forward product, three products per row for the
-        # leave-one-out products (prefix, combine, suffix), the window sums of
-        # V, and the 16-lane partial sums of V for the low columns (16 adds
-        # per component in each of the two waves); a complex product is 4
-        ops = (20 * n + 60) if cplx else (6 * n + 31)
-        achieved = ops * 2 ** (n - 1) / (ms * 1e-3) / 1e12
-        line({"row": "a10 perm + dperm/dA", "workload": f"24x24 {dtype}", "ms": ms,
-              "subset_steps_per_s": 2 ** (n - 1) / (ms * 1e-3),
-              "gemm_equivalent_tflops": gemm / (ms * 1e-3) / 1e12,
-              "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_ALU_TFLOPS,
-                           "unit": "TFLOP/s", "frac": achieved / PEAK_ALU_TFLOPS,
-                           "ops_per_subset_step": ops}})
+    print(json.dumps({"row": "next-3 DecompRyser", "workload": "40x40 0/1, 6 per row (seed 16582): "
+                      "DM pruning + Forbert-Marx, leaves batched on the GPU (host decomposition "
+                      "included)", "seconds": dt, "perm": v}), flush=True)
 
 
 # Best published GPU kernel (x_reg-A_shr-rebuild with CEG, Quadro GV100) of
@@ -409,6 +518,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched perm+grad leg")
+    ap.add_argument("--no-rows", action="store_true", help="skip the other hot-path rows")
     ap.add_argument("--paper-tables", type=str, default="",
                     help="comma-separated n: time the paper's Table 4 / Table 3 shapes and exit")
     ap.add_argument("--rows", action="store_true",
@@ -497,13 +607,19 @@ def main():
         "config": {"workload": "dense real 32x32, entries U[0,1) (seed 16578), "
                                "one perm_dense_f64 call = 2^31 subset-steps",
                    "n": N, "subset_steps_per_step": steps_per_call},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_ALU_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_ALU_TFLOPS, "traffic": traffic_bytes(),
-                     "kernel": "sweep_dense_f64<32>", "event_ms_per_launch": avg_ms,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic_bytes(),
+                     "kernel": "sweep_dense_f64<32, 0>", "event_ms_per_launch": avg_ms,
                      "flops_per_subset_step": 2 * N + 2,
-                     "frac_of_published_fp64_peak_78.6": achieved / PEAK_FMA_TFLOPS},
+                     "frac_ceiling": 0.5,
+                     "issue_slot_utilisation": achieved * 1e12 / LANE_OPS_PER_S},
         "result": float(out.item()),
     }
+    g = _golden("full_size.json")["u32"]
+    want = sum(g["value"])
+    rec["result_rel_err"] = abs(rec["result"] - want) / want
+    if not args.no_rows:
+        rec["rows"] = measure_rows()
     if not args.no_batched:
         rec["batched"] = bench_batched()
     if not args.no_cpu_baseline:

@@ -9,7 +9,7 @@
  * S, -1 when it leaves), and accumulates (-1)^g * prod_i x_i.  The permanent
  * is 2 (-1)^(n-1) times that sum.  The iteration space is split into
  * power-of-two chunks, one per GPU lane, each seeded in closed form from its
- * Gray code (Algorithm 3 with the chunking of Section 3.2).
+ * Gray code (Algorithm 3 with the chunking of Section 3.1.1).
  *
  * General conventions (all entry points):
  *   - Dense matrices are DEVICE pointers, row-major: entry (i, j) is at
@@ -19,18 +19,20 @@
  *     them before any GPU work, then stages them into the workspace.
  *   - ws is a DEVICE workspace of at least perm_workspace_bytes(kind, n, m)
  *     bytes, owned by the caller; the library allocates no device memory for
- *     data (the *_gen entry points load compiled code modules, which stay
- *     loaded) and keeps no pointer to caller memory after a call returns.
+ *     data (perm_sparse_f64 and the *_gen entry points load code modules
+ *     compiled for a sparsity pattern, which stay loaded) and keeps no
+ *     pointer to caller memory after a call returns.
  *   - stream is a hipStream_t passed as void* (NULL = the null stream).  All
- *     calls are asynchronous on that stream except perm_binary_exact, which
- *     synchronises it to finish the Chinese remaindering on the host, and
- *     perm_sparse_f64, which synchronises it once its host pattern is staged.
+ *     calls are asynchronous on that stream except perm_binary_exact(_gen),
+ *     which synchronise it to finish the Chinese remaindering on the host.
+ *     Sparse real inputs travel to the device inside kernel arguments, so
+ *     the host arrays may be reused as soon as the call returns.
  *   - Results are deterministic for fixed inputs and sizes: partial sums are
  *     combined in a fixed order and no result goes through atomics.
  *   - perm_dense_f64(_ex), perm_dense_c128, perm_grad and perm_weighted_sum
  *     only enqueue kernels (no allocation, copy, memset or synchronisation),
- *     so they can be captured into a hipGraph; the sparse and binary entry
- *     points stage host data and synchronise, so they cannot.
+ *     so they can be captured into a hipGraph; the binary entry points copy
+ *     host data and synchronise, so they cannot.
  *   - n == 0 yields 1 (the empty product); n < 0 or n > PERM_MAX_N is
  *     PERM_EINVAL.  Errors are reported as negative return values before any
  *     GPU work is queued, except PERM_EHIP which reports a HIP runtime error.
@@ -149,36 +151,39 @@ int perm_dense_c128(int n, const perm_c128 *A, int64_t lda, perm_c128 *out,
                     void *ws, size_t ws_bytes, void *stream);
 
 /*
- * Permanent of a sparse real n x n matrix in CSC (Algorithm 2, SpaRyser:
- * the same Gray walk, a step adds the nonzeros of one column to x, and the
- * product runs over all n rows).  The pattern is validated on the host and
- * staged into the workspace as column copies; the call returns once the
- * staging copy has completed (it synchronises `stream`), and the sweep then
- * runs asynchronously.  A row or column without a nonzero value gives
- * exactly 0 (written by a one-thread kernel; no sweep, no synchronisation).
+ * Permanent of a sparse real n x n matrix in CSC (Algorithm 2, SpaRyser,
+ * Section 2.1): the same Gray walk as the dense sweep, but a step adds to x
+ * only the nonzeros of the flipped column; the product still runs over all
+ * n rows.  With x held in registers a run-time row index cannot address a
+ * register, so for n >= 14 the nonzero lists of the pattern are compiled
+ * into a kernel (the per-matrix code generation of Section 3.2): the first
+ * call for a pattern on a device compiles it with hiprtc (about a second)
+ * and keeps the module loaded until the process ends; later calls with the
+ * same pattern, whatever the values, reuse it.  Columns are reordered by
+ * ascending count and rows touched by the four lowest columns are moved
+ * last (the permanent is invariant under both), so inside a 16-step block
+ * the product of the untouched rows is formed once.  For n < 14 (at most
+ * 2^12 steps) the matrix is staged as dense columns instead.
  *   col_ptr  host int32[n+1], col_ptr[0] = 0, nondecreasing, col_ptr[n] = nnz
  *   row_idx  host int32[nnz], strictly increasing within a column, in [0, n)
  *   vals     host double[nnz]
  *   out      device, one double
+ * Asynchronous: the nonzeros are copied into kernel arguments, and nothing
+ * waits for the stream.  A row or column without a nonzero value gives
+ * exactly 0 (written by a one-thread kernel, no sweep).  PERM_ECOMPILE if the
+ * run-time compilation fails (perm_sparse_f64_staged needs none).
  */
 int perm_sparse_f64(int n, const int32_t *col_ptr, const int32_t *row_idx,
                     const double *vals, int32_t nnz, double *out,
                     void *ws, size_t ws_bytes, void *stream);
 
-/* perm_sparse_f64 through a kernel generated for this sparsity pattern
- * (Section 3.3's per-matrix code generation applied to Algorithm 2's sparse
- * update): each column's update is compiled as a fixed list of additions to
- * the rows holding its nonzeros, so a step costs the column's nonzeros
- * instead of n additions.  Columns are reordered by ascending count first
- * (the permanent does not change).  The first call for a pattern on a device
- * compiles the kernel with hiprtc (about a second) and keeps it loaded until
- * the process ends; later calls with the same pattern, whatever the values,
- * reuse it.  Same arguments, workspace (PERM_KIND_SPARSE_F64) and
- * synchronisation as perm_sparse_f64; n < 14 runs perm_sparse_f64 itself.
- * PERM_ECOMPILE if the compilation fails. */
-int perm_sparse_f64_gen(int n, const int32_t *col_ptr, const int32_t *row_idx,
-                        const double *vals, int32_t nnz, double *out, void *ws, size_t ws_bytes,
-                        void *stream);
+/* The same permanent without run-time compilation: the matrix is staged as
+ * dense columns and swept by the dense kernel, so every step adds a whole
+ * column (zeros included).  Same arguments, workspace (PERM_KIND_SPARSE_F64)
+ * and asynchrony as perm_sparse_f64. */
+int perm_sparse_f64_staged(int n, const int32_t *col_ptr, const int32_t *row_idx,
+                           const double *vals, int32_t nnz, double *out, void *ws,
+                           size_t ws_bytes, void *stream);
 
 /*
  * Exact permanent of a 0/1 matrix given by its nonzero pattern in CSC (the
@@ -202,7 +207,7 @@ int perm_binary_exact(int n, const int32_t *col_ptr, const int32_t *row_idx,
                       size_t ws_bytes, void *stream);
 
 /* perm_binary_exact through a kernel generated for this 0/1 pattern (the
- * per-matrix code generation of Section 3.3 applied to the exact path):
+ * per-matrix code generation of Section 3.2 applied to the exact path):
  * columns are reordered by ascending count and the rows the four lowest
  * columns touch are moved last; each flip is a fixed list of +-2 updates on
  * the column's rows; inside a 16-step block the products of the other rows

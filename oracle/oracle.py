@@ -184,7 +184,7 @@ class Oracle:
 
     # -- Algorithm 2 ----------------------------------------------------------
     def ryser_csc(self, n: int, col_ptr, row_idx, vals, threads: int = 0,
-                  with_abs: bool = False):
+                  with_abs: bool = False, split: bool = False):
         """perm of a real matrix given by CSC columns (Algorithm 2: a step
         updates x by the flipped column's nonzeros only), long double."""
         col_ptr = np.ascontiguousarray(col_ptr, dtype=np.int32)
@@ -198,10 +198,10 @@ class Oracle:
         _check(self.lib.orc_ryser_csc_real(
             n, col_ptr.ctypes.data_as(i32), row_idx.ctypes.data_as(i32), _dptr(vals), threads,
             _dptr(out), _dptr(absum)), "ryser_csc_real")
-        v = float(out[0] + out[1])
+        v = (out[0], out[1]) if split else float(out[0] + out[1])
         return (v, float(absum[0] + absum[1])) if with_abs else v
 
-    def sparse(self, a, threads: int = 0):
+    def sparse(self, a, threads: int = 0, with_abs: bool = False, split: bool = False):
         """ryser_csc of the nonzeros of a dense real matrix."""
         r = _real(a)
         n = r.shape[0]
@@ -212,7 +212,7 @@ class Oracle:
             rows.extend(nz.tolist())
             vals.extend(r[nz, j].tolist())
             col_ptr[j + 1] = len(rows)
-        return self.ryser_csc(n, col_ptr, rows, vals, threads)
+        return self.ryser_csc(n, col_ptr, rows, vals, threads, with_abs, split)
 
     # -- exact binary ---------------------------------------------------------
     def binary(self, a01, threads: int = 0, with_nonzero: bool = False):

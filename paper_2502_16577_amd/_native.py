@@ -44,7 +44,7 @@ SIGNATURES = [
     ("perm_dense_f64_launches", _i64, [_int, _vp]),
     ("perm_dense_c128", _int, [_int, _vp, _i64, _vp, _vp, _sz, _vp]),
     ("perm_sparse_f64", _int, [_int, _vp, _vp, _vp, _i32, _vp, _vp, _sz, _vp]),
-    ("perm_sparse_f64_gen", _int, [_int, _vp, _vp, _vp, _i32, _vp, _vp, _sz, _vp]),
+    ("perm_sparse_f64_staged", _int, [_int, _vp, _vp, _vp, _i32, _vp, _vp, _sz, _vp]),
     ("perm_binary_exact", _int, [_int, _vp, _vp, _i32, _int, _vp, _vp, _vp, _vp, _sz, _vp]),
     ("perm_binary_exact_gen", _int, [_int, _vp, _vp, _i32, _int, _vp, _vp, _vp, _vp, _sz, _vp]),
     ("perm_binary_prime", _u64, [_int]),

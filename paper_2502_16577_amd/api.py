@@ -8,6 +8,7 @@ include/perm.h.
 from __future__ import annotations
 
 import ctypes
+import sys
 
 import numpy as np
 import torch
@@ -119,41 +120,34 @@ def perm_dense_c128(A: torch.Tensor, out: torch.Tensor | None = None, ws=None) -
     return out
 
 
+def _sparse_call(fn_name, n, col_ptr, row_idx, vals, device, out, ws):
+    col_ptr = np.ascontiguousarray(col_ptr, dtype=np.int32)
+    row_idx = np.ascontiguousarray(row_idx, dtype=np.int32)
+    vals = np.ascontiguousarray(vals, dtype=np.float64)
+    device = torch.device(device)
+    nnz = int(row_idx.size)
+    if out is None:
+        out = torch.empty((), dtype=torch.float64, device=device)
+    ws, need = _workspace(N.KIND_SPARSE_F64, n, nnz, device, ws)
+    st = getattr(N.lib(), fn_name)(n, col_ptr.ctypes.data if n else None,
+                                   row_idx.ctypes.data if nnz else None,
+                                   vals.ctypes.data if nnz else None, nnz, out.data_ptr(),
+                                   ws.data_ptr(), need, _stream(device))
+    N.check(st, fn_name)
+    return out
+
+
 def perm_sparse_f64(n: int, col_ptr, row_idx, vals, device="cuda:0", out=None, ws=None):
-    """Permanent of a sparse real matrix given in CSC on the host."""
-    col_ptr = np.ascontiguousarray(col_ptr, dtype=np.int32)
-    row_idx = np.ascontiguousarray(row_idx, dtype=np.int32)
-    vals = np.ascontiguousarray(vals, dtype=np.float64)
-    device = torch.device(device)
-    nnz = int(row_idx.size)
-    if out is None:
-        out = torch.empty((), dtype=torch.float64, device=device)
-    ws, need = _workspace(N.KIND_SPARSE_F64, n, nnz, device, ws)
-    st = N.lib().perm_sparse_f64(n, col_ptr.ctypes.data if n else None,
-                                 row_idx.ctypes.data if nnz else None,
-                                 vals.ctypes.data if nnz else None, nnz, out.data_ptr(),
-                                 ws.data_ptr(), need, _stream(device))
-    N.check(st, "perm_sparse_f64")
-    return out
+    """Permanent of a sparse real matrix given in CSC on the host (Algorithm
+    2: a step updates x by the flipped column's nonzeros only, through a
+    kernel compiled for the pattern; the module is cached per device and
+    pattern)."""
+    return _sparse_call("perm_sparse_f64", n, col_ptr, row_idx, vals, device, out, ws)
 
 
-def perm_sparse_f64_gen(n: int, col_ptr, row_idx, vals, device="cuda:0", out=None, ws=None):
-    """perm_sparse_f64 through a kernel generated and compiled (hiprtc) for
-    this sparsity pattern; the module is cached per device and pattern."""
-    col_ptr = np.ascontiguousarray(col_ptr, dtype=np.int32)
-    row_idx = np.ascontiguousarray(row_idx, dtype=np.int32)
-    vals = np.ascontiguousarray(vals, dtype=np.float64)
-    device = torch.device(device)
-    nnz = int(row_idx.size)
-    if out is None:
-        out = torch.empty((), dtype=torch.float64, device=device)
-    ws, need = _workspace(N.KIND_SPARSE_F64, n, nnz, device, ws)
-    st = N.lib().perm_sparse_f64_gen(n, col_ptr.ctypes.data if n else None,
-                                     row_idx.ctypes.data if nnz else None,
-                                     vals.ctypes.data if nnz else None, nnz, out.data_ptr(),
-                                     ws.data_ptr(), need, _stream(device))
-    N.check(st, "perm_sparse_f64_gen")
-    return out
+def perm_sparse_f64_staged(n: int, col_ptr, row_idx, vals, device="cuda:0", out=None, ws=None):
+    """perm_sparse_f64 without run-time compilation (dense column copies)."""
+    return _sparse_call("perm_sparse_f64_staged", n, col_ptr, row_idx, vals, device, out, ws)
 
 
 def perm(A: torch.Tensor) -> torch.Tensor:
@@ -292,11 +286,28 @@ class BatchedPlan:
         self.ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=self.device)
         self.ws_bytes = nb
 
-    def __del__(self):
+    def close(self):
+        """Destroys the C plan (it waits for the plan's last graph launch
+        first) and releases the workspace.  Idempotent."""
         h = getattr(self, "_h", None)
-        if h is not None and h.value and N is not None:  # N is None at interpreter exit
+        if h is not None and h.value:
             N.lib().perm_plan_destroy(h)
-            self._h = None
+        self._h = None
+        self.ws = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        # At interpreter exit the HIP runtime may already be shutting down:
+        # then the plan is left to the process teardown instead of calling
+        # into HIP (close() is the deterministic way to release it).
+        if sys.is_finalizing() or N is None:
+            return
+        self.close()
 
     def outputs(self, data: torch.Tensor):
         out = torch.empty(self.count, dtype=torch.complex128, device=self.device)
@@ -411,4 +422,7 @@ def perm_sparse_decomp(n: int, col_ptr, row_idx, vals, flags: int = DECOMP_DM | 
     N.check(N.lib().perm_weighted_sum(len(ks), w.data_ptr(), perms.data_ptr(), out.data_ptr(),
                                       _stream(device)), "perm_weighted_sum")
     torch.cuda.current_stream(device).synchronize()  # keep plan / weights alive until done
+    for obj in keep:
+        if isinstance(obj, BatchedPlan):
+            obj.close()
     return out.real.clone()

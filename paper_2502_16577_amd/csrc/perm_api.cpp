@@ -13,7 +13,7 @@
 
 namespace perm {
 
-// Lanes x chunk = 2^(n-1) exactly (Section 3.2: with power-of-two chunks every
+// Lanes x chunk = 2^(n-1) exactly (Section 3.1.1: with power-of-two chunks every
 // lane of a wave flips the same column at the same local step, and no
 // remainder kernel is needed).  About 2^18 lanes fill the 256 CUs with four
 // waves per SIMD; smaller problems use fewer lanes but at least one block and
@@ -315,44 +315,46 @@ static bool has_empty_line(int n, const int32_t *col_ptr, const int32_t *row_idx
     return false;
 }
 
-int perm_sparse_f64(int n, const int32_t *col_ptr, const int32_t *row_idx, const double *vals,
-                    int32_t nnz, double *out, void *ws, size_t ws_bytes, void *stream)
+// Validation shared by the sparse real entry points; PERM_OK to go on.
+static int sparse_args(int n, const int32_t *col_ptr, const int32_t *row_idx, const double *vals,
+                       int32_t nnz, double *out, void *ws, size_t ws_bytes)
 {
     if (!valid_n(n) || !out) return PERM_EINVAL;
     if (n > 0 && (!valid_csc(n, col_ptr, row_idx, nnz) || (nnz > 0 && !vals))) return PERM_EINVAL;
-    const int w = check_ws(ws, ws_bytes, perm_workspace_bytes(PERM_KIND_SPARSE_F64, n, nnz));
-    if (w != PERM_OK) return w;
+    return check_ws(ws, ws_bytes, perm_workspace_bytes(PERM_KIND_SPARSE_F64, n, nnz));
+}
+
+// Staged-column sweep: the matrix is scattered into a row-major copy behind
+// the dense workspace and swept like a dense matrix (every step adds a whole
+// column, zeros included).  Used for n < kSparseGenMinN (at most 2^12 steps)
+// and by perm_sparse_f64_staged.
+static int sparse_staged(int n, const int32_t *col_ptr, const int32_t *row_idx,
+                         const double *vals, char *base, double *out, hipStream_t st)
+{
+    const size_t off = perm_workspace_bytes(PERM_KIND_DENSE_F64, n, 0);
+    double *dense = reinterpret_cast<double *>(base + off);
+    const int32_t nnz = col_ptr[n];
+    std::vector<int32_t> pos(nnz);
+    for (int j = 0; j < n; ++j)
+        for (int32_t q = col_ptr[j]; q < col_ptr[j + 1]; ++q) pos[q] = row_idx[q] * n + j;
+    int rc = launch_stage_sparse(n, pos.data(), vals, nnz, dense, st);
+    if (rc != PERM_OK) return rc;
+    return launch_dense_f64(n, dense, n, out, base, st);
+}
+
+int perm_sparse_f64(int n, const int32_t *col_ptr, const int32_t *row_idx, const double *vals,
+                    int32_t nnz, double *out, void *ws, size_t ws_bytes, void *stream)
+{
+    int rc = sparse_args(n, col_ptr, row_idx, vals, nnz, out, ws, ws_bytes);
+    if (rc != PERM_OK) return rc;
     hipStream_t st = static_cast<hipStream_t>(stream);
     char *base = static_cast<char *>(ws);
     if (n == 0) return launch_dense_f64(0, nullptr, 0, out, base, st);
     if (has_empty_line(n, col_ptr, row_idx, vals)) return launch_write_f64(0.0, out, st);
-    // Stage the matrix row-major behind the dense workspace; the sweep then
-    // updates x with whole columns held in scalar registers (zeros included).
-    const size_t off = perm_workspace_bytes(PERM_KIND_DENSE_F64, n, 0);
-    std::vector<double> dense(size_t(n) * n, 0.0);
-    for (int j = 0; j < n; ++j)
-        for (int32_t q = col_ptr[j]; q < col_ptr[j + 1]; ++q) dense[size_t(row_idx[q]) * n + j] = vals[q];
-    if (hipMemcpyAsync(base + off, dense.data(), dense.size() * sizeof(double),
-                       hipMemcpyHostToDevice, st) != hipSuccess)
-        return PERM_EHIP;
-    // the host staging buffer must outlive the copy
-    if (hipStreamSynchronize(st) != hipSuccess) return PERM_EHIP;
-    return launch_dense_f64(n, reinterpret_cast<const double *>(base + off), n, out, base, st);
-}
-
-int perm_sparse_f64_gen(int n, const int32_t *col_ptr, const int32_t *row_idx,
-                        const double *vals, int32_t nnz, double *out, void *ws, size_t ws_bytes,
-                        void *stream)
-{
-    if (!valid_n(n) || !out) return PERM_EINVAL;
-    if (n > 0 && (!valid_csc(n, col_ptr, row_idx, nnz) || (nnz > 0 && !vals))) return PERM_EINVAL;
-    const int w = check_ws(ws, ws_bytes, perm_workspace_bytes(PERM_KIND_SPARSE_F64, n, nnz));
-    if (w != PERM_OK) return w;
-    if (n < kSparseGenMinN)  // a few thousand steps: the staged-column sweep
-        return perm_sparse_f64(n, col_ptr, row_idx, vals, nnz, out, ws, ws_bytes, stream);
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    if (has_empty_line(n, col_ptr, row_idx, vals)) return launch_write_f64(0.0, out, st);
-    char *base = static_cast<char *>(ws);
+    if (n < kSparseGenMinN) return sparse_staged(n, col_ptr, row_idx, vals, base, out, st);
+    // Algorithm 2's update: a step adds only the flipped column's nonzeros.
+    // With x in registers a run-time row index cannot name a register, so
+    // the update lists are compiled into a kernel for this pattern.
     // Columns by ascending count (the permanent is invariant under column
     // permutations): the low columns, flipped at 15 of every 16 steps, then
     // cost the fewest updates, and the densest column is the never-flipped
@@ -377,24 +379,39 @@ int perm_sparse_f64_gen(int n, const int32_t *col_ptr, const int32_t *row_idx,
         for (int i = 0; i < n; ++i)
             if (hot[i]) new_row[i] = k++;
     }
-    const size_t off = perm_workspace_bytes(PERM_KIND_DENSE_F64, n, 0);
-    std::vector<double> dense(size_t(n) * n, 0.0);
+    std::vector<int32_t> pos;
+    std::vector<double> val;
+    pos.reserve(nnz);
+    val.reserve(nnz);
     std::vector<std::vector<int>> rows(n);
     for (int jn = 0; jn < n; ++jn) {
         const int j = order[jn];
         for (int32_t q = col_ptr[j]; q < col_ptr[j + 1]; ++q) {
             const int i = new_row[row_idx[q]];
-            dense[size_t(i) * n + jn] = vals[q];
+            pos.push_back(i * n + jn);
+            val.push_back(vals[q]);
             rows[jn].push_back(i);
         }
         std::sort(rows[jn].begin(), rows[jn].end());
     }
-    if (hipMemcpyAsync(base + off, dense.data(), dense.size() * sizeof(double),
-                       hipMemcpyHostToDevice, st) != hipSuccess)
-        return PERM_EHIP;
-    if (hipStreamSynchronize(st) != hipSuccess) return PERM_EHIP;  // staging buffer lifetime
-    return launch_sparse_gen(n, rows, reinterpret_cast<const double *>(base + off),
-                             out, base, st);
+    const size_t off = perm_workspace_bytes(PERM_KIND_DENSE_F64, n, 0);
+    double *dense = reinterpret_cast<double *>(base + off);
+    rc = launch_stage_sparse(n, pos.data(), val.data(), int64_t(pos.size()), dense, st);
+    if (rc != PERM_OK) return rc;
+    return launch_sparse_gen(n, rows, dense, out, base, st);
+}
+
+int perm_sparse_f64_staged(int n, const int32_t *col_ptr, const int32_t *row_idx,
+                           const double *vals, int32_t nnz, double *out, void *ws,
+                           size_t ws_bytes, void *stream)
+{
+    int rc = sparse_args(n, col_ptr, row_idx, vals, nnz, out, ws, ws_bytes);
+    if (rc != PERM_OK) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char *base = static_cast<char *>(ws);
+    if (n == 0) return launch_dense_f64(0, nullptr, 0, out, base, st);
+    if (has_empty_line(n, col_ptr, row_idx, vals)) return launch_write_f64(0.0, out, st);
+    return sparse_staged(n, col_ptr, row_idx, vals, base, out, st);
 }
 
 // The exact binary path; `generated` selects the kernel generated for the

@@ -51,6 +51,9 @@ struct perm_plan {
     hipStream_t side[kBatchGroups] = {nullptr, nullptr, nullptr};
     hipStream_t capture = nullptr;
     hipEvent_t fork = nullptr, join[kBatchGroups] = {nullptr, nullptr, nullptr};
+    // recorded after every graph launch: the graph's work is finished once
+    // it completes (waited for before the graph or the streams are destroyed)
+    hipEvent_t launched = nullptr;
 };
 
 namespace {
@@ -120,8 +123,15 @@ void derive(perm_plan &P)
     P.total = o;
 }
 
+// Waits for the last graph launch of the plan (if any) to finish.
+void wait_graph(perm_plan &P)
+{
+    if (P.exec && P.launched) hipEventSynchronize(P.launched);
+}
+
 void drop_graph(perm_plan &P)
 {
+    wait_graph(P);
     if (P.exec) hipGraphExecDestroy(P.exec);
     P.exec = nullptr;
     P.g_data = P.g_out = P.g_grad = P.g_ws = nullptr;
@@ -199,7 +209,11 @@ int perm_batched_plan_create(int count, const int32_t *k, const int64_t *offset,
 void perm_plan_destroy(perm_plan *plan)
 {
     if (!plan) return;
+    // No plan-owned object is released while a graph launch that uses it is
+    // still queued or running: drop_graph waits for the last launch first,
+    // and the side streams (used only while capturing) are idle after it.
     drop_graph(*plan);
+    if (plan->launched) hipEventDestroy(plan->launched);
     for (int g = 0; g < kBatchGroups; ++g) {
         if (plan->side[g]) hipStreamDestroy(plan->side[g]);
         if (plan->join[g]) hipEventDestroy(plan->join[g]);
@@ -231,6 +245,8 @@ int perm_batched(perm_plan *plan, const perm_c128 *data, perm_c128 *out, perm_c1
             return PERM_EHIP;
         if (!P.fork && hipEventCreateWithFlags(&P.fork, hipEventDisableTiming) != hipSuccess)
             return PERM_EHIP;
+        if (!P.launched && hipEventCreateWithFlags(&P.launched, hipEventDisableTiming) != hipSuccess)
+            return PERM_EHIP;
         for (int g = 0; g < kBatchGroups; ++g) {
             if (!P.side[g] && hipStreamCreateWithFlags(&P.side[g], hipStreamNonBlocking) != hipSuccess)
                 return PERM_EHIP;
@@ -257,7 +273,8 @@ int perm_batched(perm_plan *plan, const perm_c128 *data, perm_c128 *out, perm_c1
         P.g_grad = grad;
         P.g_ws = ws;
     }
-    return hipGraphLaunch(P.exec, st) == hipSuccess ? PERM_OK : PERM_EHIP;
+    if (hipGraphLaunch(P.exec, st) != hipSuccess) return PERM_EHIP;
+    return hipEventRecord(P.launched, st) == hipSuccess ? PERM_OK : PERM_EHIP;
 }
 
 int perm_batched_autotune(perm_plan *plan, const perm_c128 *data, perm_c128 *out,

@@ -201,6 +201,18 @@ std::string binary_gen_source(int n, int n_cold, const std::vector<std::vector<i
 
 // out[0] = v (a kernel, so it can sit in a captured graph).
 int launch_write_f64(double v, double *out, hipStream_t stream);
+// Stages count entries into the row-major n x n copy `dense` (device):
+// zeroes it, then dense[pos[t]] = val[t].  pos / val are host arrays whose
+// contents are copied into the kernel arguments, so they may be released as
+// soon as the call returns (no synchronisation).
+constexpr int kScatterChunk = 256;
+struct ScatterChunk {
+    int count;
+    int32_t pos[kScatterChunk];
+    double val[kScatterChunk];
+};
+int launch_stage_sparse(int n, const int32_t *pos, const double *val, int64_t count,
+                        double *dense, hipStream_t stream);
 int launch_dense_f64(int n, const double *A, int64_t lda, double *out, char *ws,
                      hipStream_t stream);
 int launch_dense_f64_opt(int n, const double *A, int64_t lda, double *out, const SweepOptions &o,

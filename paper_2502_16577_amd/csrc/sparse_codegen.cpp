@@ -1,5 +1,5 @@
 // Matrix-specific sparse sweep (the paper's per-matrix code generation,
-// Section 3.3, applied to the sparse update of Algorithm 2): the host writes
+// Section 3.2, applied to the sparse update of Algorithm 2): the host writes
 // a HIP kernel in which the update of every column is a fixed list of
 // `x_r += a_rj` on named registers -- only the column's nonzeros, with
 // compile-time row indices -- compiles it for gfx950 with hiprtc, and keeps

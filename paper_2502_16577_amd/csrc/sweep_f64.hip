@@ -1,6 +1,6 @@
 // Dense real FP64 permanent: the Gray-code Ryser / Nijenhuis-Wilf sweep
 // (Algorithm 1 of arXiv 2502.16577, chunked as in Algorithm 3 with the
-// power-of-two chunks of Section 3.2).
+// power-of-two chunks of Section 3.1.1).
 //
 // Data layout in HBM (all inside the caller's workspace):
 //   acol[j*N + i] = a_ij   (column-major, so one Gray step reads one
@@ -9,7 +9,7 @@
 //   partials[b] = double-double sum of block b
 //
 // Per lane: x[N] lives in VGPRs (N is a template parameter, the analogue of
-// the paper's per-matrix rebuild of Section 3.3).  Because the chunk length is
+// the paper's per-matrix rebuild of Section 3.2).  Because the chunk length is
 // a power of two and bit 0 of the chunk index is shared by the whole wave,
 // the flipped column j = ctz(l) and its sign are wave-uniform at every step,
 // so the column is fetched with scalar loads into SGPRs and feeds v_add_f64

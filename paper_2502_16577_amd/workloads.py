@@ -41,6 +41,8 @@ SEED_HAAR120 = 16581
 SEED_SPARSE40 = 16582
 SEED_HAAR64 = 16583
 SEED_BATCH = 16584
+# values of the sparse 40 x 40 pattern when it is run as a real matrix
+SEED_SPARSE40_VALUES = 16585
 
 
 def uniform(n: int, seed: int) -> np.ndarray:

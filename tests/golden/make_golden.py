@@ -35,6 +35,9 @@ def inputs():
         # Table 4 shapes (dense U[0,1), one matrix per order, seed 1000 + n)
         "u35": lambda: W.uniform(35, 1035),
         "u40": lambda: W.uniform(40, 1040),
+        # the 40x40 sparse pattern with U[0,1) values (Algorithm 2's CSC walk)
+        "sparse40u": lambda: (W.sparse_rows(40, 6, W.SEED_SPARSE40)
+                              * W.uniform(40, W.SEED_SPARSE40_VALUES)),
     }
 
 
@@ -44,6 +47,9 @@ def run(name, a, orc):
     if a.dtype == np.uint8:
         v, nz = orc.binary(a, with_nonzero=True)
         rec.update(kind="binary", value=str(v), nonzero_terms=nz)
+    elif name.startswith("sparse"):
+        (h, l), r = orc.sparse(a, with_abs=True, split=True)
+        rec.update(kind="real", value=[h, l], abs_sum=r, abs_perm=h + l, oracle="ryser_csc")
     elif np.iscomplexobj(a):
         (rh, rl, ih, il), r = orc.ryser(a, with_abs=True, split=True)
         rec.update(kind="complex", re=[rh, rl], im=[ih, il], abs_sum=r,

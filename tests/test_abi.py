@@ -136,7 +136,7 @@ def test_binary_primes_are_primes_above_2_50():
     assert lib.perm_binary_prime(6) == 0 and lib.perm_binary_prime(-1) == 0
 
 
-@pytest.mark.parametrize("name", ["perm_sparse_f64", "perm_sparse_f64_gen"])
+@pytest.mark.parametrize("name", ["perm_sparse_f64", "perm_sparse_f64_staged"])
 def test_sparse_argument_errors(name):
     import numpy as np
     lib = N.lib()

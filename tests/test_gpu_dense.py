@@ -150,6 +150,24 @@ def test_options_plain_and_split(oracle):
             assert abs(v - want) <= 1e-10 * abs(want), (acc, r, v, want)
 
 
+@pytest.mark.parametrize("name", ["u35"])
+def test_table4_shapes_against_oracle(name):
+    # Table 4 shapes (Section 6.1): a dense U[0,1) matrix of order n (seed
+    # 1000 + n), 2^(n-1) subset-steps, against the stored oracle value; the
+    # default sweep and the two other lane accumulation modes
+    g = _golden(name)
+    n = g["n"]
+    a = W.uniform(n, 1000 + n)
+    assert W.digest(a) == g["digest"]
+    want = g["value"][0] + g["value"][1]
+    A = torch.from_numpy(a).to(DEV)
+    got = api.perm_dense_f64(A).item()
+    assert abs(got - want) <= 1e-10 * abs(want), (n, got, want, abs(got - want) / want)
+    for acc in (api.ACC_KAHAN, api.ACC_PLAIN):
+        v = api.perm_dense_f64_ex(A, accumulation=acc).item()
+        assert abs(v - want) <= 1e-10 * abs(want), (n, acc, v, want, abs(v - want) / want)
+
+
 @pytest.mark.parametrize("n", [35, 36])
 def test_all_equal_paper_size(n):
     # Section 5 / Table 3 shapes: all entries 0.91, perm = n! 0.91^n (2^34 and 2^35 steps)
@@ -196,7 +214,7 @@ def test_empty_and_degenerate_inputs():
                 ri += nz; va += vals; cp.append(len(ri))
             cp, ri, va = np.array(cp, np.int32), np.array(ri, np.int32), np.array(va)
             assert api.perm_sparse_f64(n, cp, ri, va).item() == 0.0, (n, case)
-            assert api.perm_sparse_f64_gen(n, cp, ri, va).item() == 0.0, (n, case)
+            assert api.perm_sparse_f64_staged(n, cp, ri, va).item() == 0.0, (n, case)
 
 
 def test_graph_capture_replays():

@@ -41,7 +41,7 @@ def rel(a, b):
     return abs(a - b) / max(abs(b), 1e-300)
 
 
-# --- Section 2, Table 1 and the CBL recursion of Section 3.2 ---------------
+# --- Section 2, Table 1 and the CBL recursion of Section 3.1.1 ---------------
 
 def test_table1_gray_codes(oracle):
     for g, binary, gray, changed in _fixture_rows("paper_table1_gray3.txt"):

@@ -1,4 +1,4 @@
-"""Host-side checks of the chunk partition (Section 3.2, Algorithm 3) that the
+"""Host-side checks of the chunk partition (Section 3.1.1, Algorithm 3) that the
 kernels rely on: with power-of-two chunks every thread flips the same column
 at every local step (the paper's CEG claim), and with the kernels' lane
 numbering the flip's sign is the same across the 64 lanes of a wave too, so
@@ -21,7 +21,7 @@ def distinct_columns(chunk: int, threads: int):
 
 
 def test_paper_ceg_claims():
-    # Section 3.2: a chunk of 17 over 4 threads gives 3 different columns at
+    # Section 3.1.1: a chunk of 17 over 4 threads gives 3 different columns at
     # every local iteration; a chunk of 16 gives one column except the last
     assert distinct_columns(17, 4) == [3] * 17
     assert distinct_columns(16, 4) == [1] * 15 + [3]
