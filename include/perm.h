@@ -281,18 +281,29 @@ int perm_batched(perm_plan *plan, const perm_c128 *data, perm_c128 *out, perm_c1
                  int use_graph, void *ws, size_t ws_bytes, void *stream);
 
 /*
- * Autotuner: times the batch for every candidate of (steps per lane,
- * persistent grid size) on this device and keeps the fastest in the plan.
- * Synchronises `stream`; writes the outputs as a side effect.  best_ms
+ * Autotuner: times the batch on this device as the graph runs it (each
+ * group's persistent kernel on its own stream, concurrently) and keeps the
+ * fastest configuration in the plan, searching one knob at a time from the
+ * defaults: the Gray steps per lane (2^8, 2^10, 2^12), then the persistent
+ * grid of each group that has work (orders 1..16: 512 / 1024 / 2048 blocks;
+ * 17..24: 512 / 768 / 1024, i.e. 1, 1.5 or 2 waves per SIMD; 25..32: 256 /
+ * 384 / 512).  The result is kept for the rest of the process, keyed by
+ * (device, want_grad, histogram of the orders): a plan created later with
+ * the same key starts from it, and autotuning such a plan returns the
+ * stored configuration and time without running anything.  Otherwise it
+ * synchronises `stream` and writes the outputs as a side effect.  best_ms
  * (nullable) receives the time of the chosen configuration.
  */
 int perm_batched_autotune(perm_plan *plan, const perm_c128 *data, perm_c128 *out,
                           perm_c128 *grad, void *ws, size_t ws_bytes, void *stream,
                           double *best_ms);
 
-/* Plan introspection: number of work items, chosen log2 steps per lane, grid. */
+/* Plan introspection (any output may be NULL): number of work items, log2
+ * steps per lane, grid[3] = persistent blocks of the groups of orders 1..16,
+ * 17..24 and 25..32, and whether the configuration came from the tuning
+ * kept by an earlier perm_batched_autotune in this process. */
 int perm_batched_plan_info(const perm_plan *plan, int64_t *n_items, int *log2_chunk,
-                           int64_t *grid_small);
+                           int64_t *grid, int *tuned_from_cache);
 
 /* out = sum_m weights[m] * perms[m] over count >= 1 device values, in
  * double-double and a fixed order (used to combine the leaves of a

@@ -337,10 +337,17 @@ class BatchedPlan:
         return best.value
 
     def info(self):
-        ni, lc, gs = ctypes.c_int64(), ctypes.c_int(), ctypes.c_int64()
+        """Work items, log2 steps per lane, persistent grid per group of
+        orders (1..16, 17..24, 25..32) and whether the tuning came from an
+        earlier autotune in this process."""
+        ni, lc, fc = ctypes.c_int64(), ctypes.c_int(), ctypes.c_int()
+        grid = np.zeros(3, np.int64)
         N.check(N.lib().perm_batched_plan_info(self._h, ctypes.byref(ni), ctypes.byref(lc),
-                                               ctypes.byref(gs)), "perm_batched_plan_info")
-        return {"items": ni.value, "log2_chunk": lc.value, "grid_small": gs.value}
+                                               grid.ctypes.data, ctypes.byref(fc)),
+                "perm_batched_plan_info")
+        return {"items": ni.value, "log2_chunk": lc.value,
+                "grid": {"k1_16": int(grid[0]), "k17_24": int(grid[1]), "k25_32": int(grid[2])},
+                "tuned_from_cache": bool(fc.value)}
 
 
 DECOMP_DM = 1

@@ -4,8 +4,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <iterator>
+#include <array>
 #include <cstring>
+#include <iterator>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "batched_internal.h"
@@ -16,15 +19,40 @@ using namespace perm;
 namespace {
 
 // Tuning knobs.  log2_chunk is the number of Gray steps per lane (log2) used
-// for large matrices; the grids are persistent one-wave blocks per group.
+// for large matrices; grid[g] is the number of persistent two-wave blocks of
+// group g's kernel, which sets how many waves each SIMD runs (the kernels of
+// orders 1..24 fit two waves per SIMD, 1024 blocks on 256 CUs; the kernel of
+// orders 25..32 one, 512 blocks).
 struct BatchTuning {
     int log2_chunk = 10;
-    int64_t grid[kBatchGroups] = {2048, 1024, 1024};
+    int64_t grid[kBatchGroups] = {2048, 1024, 512};
 };
 
-// Candidates the autotuner times.
+// Candidates the autotuner times, one knob at a time (coordinate descent
+// from the defaults): steps per lane, then each group's grid.
 const int kTuneChunks[] = {8, 10, 12};
-const int64_t kTuneGridSmall[] = {1024, 2048};
+const int64_t kTuneGrid[kBatchGroups][3] = {{512, 1024, 2048}, {512, 768, 1024}, {256, 384, 512}};
+
+// Tunings found by perm_batched_autotune, kept for the process and keyed by
+// (device, gradient or not, histogram of the orders): a later plan with the
+// same key starts from the tuned values and its autotune call returns at once.
+struct TuneKey {
+    int device = 0;
+    int want_grad = 0;
+    std::array<int32_t, kBatchMaxK + 1> hist{};
+    bool operator<(const TuneKey &o) const
+    {
+        if (device != o.device) return device < o.device;
+        if (want_grad != o.want_grad) return want_grad < o.want_grad;
+        return hist < o.hist;
+    }
+};
+struct TuneEntry {
+    BatchTuning tune;
+    double ms = 0.0;
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneEntry> g_tune_cache;
 
 }  // namespace
 
@@ -54,6 +82,7 @@ struct perm_plan {
     // recorded after every graph launch: the graph's work is finished once
     // it completes (waited for before the graph or the streams are destroyed)
     hipEvent_t launched = nullptr;
+    int tuned_from_cache = 0;  // 1: the tuning came from the process-wide cache
 };
 
 namespace {
@@ -154,6 +183,34 @@ int upload(perm_plan &P, char *ws, hipStream_t st)
     return PERM_OK;
 }
 
+TuneKey tune_key(const perm_plan &P)
+{
+    TuneKey key;
+    hipGetDevice(&key.device);
+    key.want_grad = P.want_grad;
+    for (int k : P.k) key.hist[k]++;
+    return key;
+}
+
+// The plan's side streams and events (created once, reused by every graph
+// capture and every tuning launch).
+int ensure_streams(perm_plan &P)
+{
+    if (!P.capture && hipStreamCreateWithFlags(&P.capture, hipStreamNonBlocking) != hipSuccess)
+        return PERM_EHIP;
+    if (!P.fork && hipEventCreateWithFlags(&P.fork, hipEventDisableTiming) != hipSuccess)
+        return PERM_EHIP;
+    if (!P.launched && hipEventCreateWithFlags(&P.launched, hipEventDisableTiming) != hipSuccess)
+        return PERM_EHIP;
+    for (int g = 0; g < kBatchGroups; ++g) {
+        if (!P.side[g] && hipStreamCreateWithFlags(&P.side[g], hipStreamNonBlocking) != hipSuccess)
+            return PERM_EHIP;
+        if (!P.join[g] && hipEventCreateWithFlags(&P.join[g], hipEventDisableTiming) != hipSuccess)
+            return PERM_EHIP;
+    }
+    return PERM_OK;
+}
+
 BatchLaunch make_launch(const perm_plan &P, char *ws, const perm_c128 *data, perm_c128 *out,
                         perm_c128 *grad)
 {
@@ -200,6 +257,14 @@ int perm_batched_plan_create(int count, const int32_t *k, const int64_t *offset,
     derive(*P);
     const size_t mx = P->total;
     P->tune = BatchTuning{};
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        auto it = g_tune_cache.find(tune_key(*P));
+        if (it != g_tune_cache.end()) {
+            P->tune = it->second.tune;
+            P->tuned_from_cache = 1;
+        }
+    }
     derive(*P);
     P->ws_max = std::max(mx, P->total);
     *plan = P;
@@ -241,18 +306,7 @@ int perm_batched(perm_plan *plan, const perm_c128 *data, perm_c128 *out, perm_c1
 
     if (!P.exec || P.g_data != data || P.g_out != out || P.g_grad != grad || P.g_ws != ws) {
         drop_graph(P);
-        if (!P.capture && hipStreamCreateWithFlags(&P.capture, hipStreamNonBlocking) != hipSuccess)
-            return PERM_EHIP;
-        if (!P.fork && hipEventCreateWithFlags(&P.fork, hipEventDisableTiming) != hipSuccess)
-            return PERM_EHIP;
-        if (!P.launched && hipEventCreateWithFlags(&P.launched, hipEventDisableTiming) != hipSuccess)
-            return PERM_EHIP;
-        for (int g = 0; g < kBatchGroups; ++g) {
-            if (!P.side[g] && hipStreamCreateWithFlags(&P.side[g], hipStreamNonBlocking) != hipSuccess)
-                return PERM_EHIP;
-            if (!P.join[g] && hipEventCreateWithFlags(&P.join[g], hipEventDisableTiming) != hipSuccess)
-                return PERM_EHIP;
-        }
+        if ((rc = ensure_streams(P)) != PERM_OK) return rc;
         hipGraph_t graph = nullptr;
         if (hipStreamBeginCapture(P.capture, hipStreamCaptureModeThreadLocal) != hipSuccess)
             return PERM_EHIP;
@@ -285,43 +339,84 @@ int perm_batched_autotune(perm_plan *plan, const perm_c128 *data, perm_c128 *out
     if (plan->want_grad && !grad) return PERM_EINVAL;
     if (!ws || ws_bytes < plan->ws_max) return PERM_EWORKSPACE;
     perm_plan &P = *plan;
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    char *base = static_cast<char *>(ws);
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return PERM_EHIP;
-    BatchTuning best = P.tune;
-    float best_t = 1e30f;
-    int rc = PERM_OK;
-    for (int ct : kTuneChunks) {
-        for (int64_t gs : kTuneGridSmall) {
-            P.tune.log2_chunk = ct;
-            P.tune.grid[0] = gs;
+    const TuneKey key = tune_key(P);
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            wait_graph(P);
+            P.tune = it->second.tune;
+            P.tuned_from_cache = 1;
             derive(P);
             P.uploaded_ws = nullptr;
-            if ((rc = upload(P, base, st)) != PERM_OK) break;
-            const BatchLaunch L = make_launch(P, base, data, out, grad);
-            if ((rc = launch_batched(L, st)) != PERM_OK) break;  // warm-up
-            hipEventRecord(e0, st);
-            for (int rep = 0; rep < 2 && rc == PERM_OK; ++rep) rc = launch_batched(L, st);
-            hipEventRecord(e1, st);
-            if (hipEventSynchronize(e1) != hipSuccess) rc = PERM_EHIP;
-            if (rc != PERM_OK) break;
+            drop_graph(P);
+            if (best_ms) *best_ms = it->second.ms;
+            return PERM_OK;
+        }
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char *base = static_cast<char *>(ws);
+    int rc = ensure_streams(P);
+    if (rc != PERM_OK) return rc;
+    drop_graph(P);  // waits for the last graph launch before the workspace is reused
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return PERM_EHIP;
+    // Times one candidate as the graph runs it: the groups' persistent
+    // kernels on their forked streams, concurrently (one untimed launch,
+    // then the average of two).
+    auto time_it = [&](const BatchTuning &t, float &ms) -> int {
+        P.tune = t;
+        derive(P);
+        P.uploaded_ws = nullptr;
+        int r = upload(P, base, st);
+        if (r != PERM_OK) return r;
+        const BatchLaunch L = make_launch(P, base, data, out, grad);
+        if ((r = launch_batched_forked(L, st, P.side, P.fork, P.join)) != PERM_OK) return r;
+        if (hipEventRecord(e0, st) != hipSuccess) return PERM_EHIP;
+        for (int rep = 0; rep < 2; ++rep)
+            if ((r = launch_batched_forked(L, st, P.side, P.fork, P.join)) != PERM_OK) return r;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+            return PERM_EHIP;
+        hipEventElapsedTime(&ms, e0, e1);
+        ms *= 0.5f;
+        return PERM_OK;
+    };
+    BatchTuning best = P.tune;
+    float best_t = 1e30f;
+    rc = time_it(best, best_t);
+    // one knob at a time: steps per lane, then the grid of each group that
+    // has work (largest orders first)
+    for (int knob = -1; knob < kBatchGroups && rc == PERM_OK; ++knob) {
+        if (knob >= 0) {
+            bool any = false;
+            for (int k : P.k) any = any || batch_group(k) == knob;
+            if (!any) continue;
+        }
+        const int ncand = knob < 0 ? int(std::size(kTuneChunks)) : 3;
+        for (int c = 0; c < ncand && rc == PERM_OK; ++c) {
+            BatchTuning t = best;
+            if (knob < 0) t.log2_chunk = kTuneChunks[c];
+            else t.grid[knob] = kTuneGrid[knob][c];
+            if (knob < 0 ? t.log2_chunk == best.log2_chunk : t.grid[knob] == best.grid[knob])
+                continue;
             float ms = 0.f;
-            hipEventElapsedTime(&ms, e0, e1);
-            ms *= 0.5f;
-            if (ms < best_t) {
+            rc = time_it(t, ms);
+            if (rc == PERM_OK && ms < best_t) {
                 best_t = ms;
-                best = P.tune;
+                best = t;
             }
         }
-        if (rc != PERM_OK) break;
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     P.tune = best;
     derive(P);
     P.uploaded_ws = nullptr;
-    drop_graph(P);
+    if (rc == PERM_OK) {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        g_tune_cache[key] = TuneEntry{best, double(best_t)};
+        P.tuned_from_cache = 0;
+    }
     if (best_ms) *best_ms = best_t;
     return rc;
 }
@@ -334,12 +429,14 @@ int perm_weighted_sum(int count, const double *weights, const perm_c128 *perms, 
 }
 
 int perm_batched_plan_info(const perm_plan *plan, int64_t *n_items, int *log2_chunk,
-                           int64_t *grid_small)
+                           int64_t *grid, int *tuned_from_cache)
 {
     if (!plan) return PERM_EINVAL;
     if (n_items) *n_items = plan->n_items_total;
     if (log2_chunk) *log2_chunk = plan->tune.log2_chunk;
-    if (grid_small) *grid_small = plan->tune.grid[0];
+    if (grid)
+        for (int g = 0; g < kBatchGroups; ++g) grid[g] = plan->tune.grid[g];
+    if (tuned_from_cache) *tuned_from_cache = plan->tuned_from_cache;
     return PERM_OK;
 }
 

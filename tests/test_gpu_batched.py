@@ -2,6 +2,7 @@
 single-matrix paths and the oracle."""
 import json
 import os
+import time
 
 import numpy as np
 import pytest
@@ -101,13 +102,31 @@ def test_graph_replays_match_eager():
 
 
 def test_autotune_keeps_results():
-    mats = mixed_batch([10, 16, 21, 23], 71)
+    mats = mixed_batch([10, 16, 21, 23, 26], 71)
     out0, g0, _ = run(mats)
     out1, g1, info = run(mats, autotune=True)
     assert info["log2_chunk"] in (8, 10, 12)
+    assert info["grid"]["k1_16"] in (512, 1024, 2048)
+    assert info["grid"]["k17_24"] in (512, 768, 1024)
+    assert info["grid"]["k25_32"] in (256, 384, 512)
     for m in range(len(mats)):
         assert abs(out1[m] - out0[m]) <= 1e-12 * abs(out0[m])
         assert np.max(np.abs(g1[m] - g0[m])) <= 1e-11 * np.max(np.abs(g0[m]))
+    # the tuning is kept for plans with the same orders on this device
+    ks, offs, data = W.pack(mats)
+    with api.BatchedPlan(ks, offs, want_grad=True) as plan:
+        i2 = plan.info()
+        assert i2["tuned_from_cache"]
+        assert (i2["log2_chunk"], i2["grid"]) == (info["log2_chunk"], info["grid"])
+        d = torch.from_numpy(data).to(DEV)
+        t0 = time.perf_counter()
+        plan.autotune(d)  # returns the kept configuration without timing anything
+        assert time.perf_counter() - t0 < 0.05
+        out2, _ = plan.run(d)
+        assert np.array_equal(out2.cpu().numpy(), out1)
+    # another set of orders is not affected
+    with api.BatchedPlan(ks[:-1], offs[:-1], want_grad=True) as plan:
+        assert not plan.info()["tuned_from_cache"]
 
 
 def test_full_config_4096():
