@@ -62,6 +62,7 @@ typedef struct {
 #define PERM_EHIP         -4  /* a HIP runtime call failed */
 #define PERM_EUNSUPPORTED -5  /* valid request the library does not implement */
 #define PERM_ECOMPILE     -6  /* run-time compilation of a generated kernel failed */
+#define PERM_ESCRATCH     -7  /* request exceeds the fixed scratch of an allocation-free entry point */
 
 /* Workspace kinds for perm_workspace_bytes(). */
 #define PERM_KIND_DENSE_F64   1
@@ -97,6 +98,27 @@ size_t perm_workspace_bytes(int kind, int n, int64_t m);
  */
 int perm_dense_f64(int n, const double *A, int64_t lda, double *out,
                    void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * perm_dense_f64 for callers that cannot allocate device memory (code under
+ * hipGraph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the workspace lives in a fixed array of perm_noalloc_scratch_bytes() bytes
+ * inside the library's device memory, one copy per GPU, held until the
+ * process ends.  The caller passes only the input and the output.  Same
+ * kernels and result as perm_dense_f64 with a caller workspace.
+ *   A, lda, out, stream  as for perm_dense_f64 (the current device's array
+ *                        is used; the stream must belong to that device)
+ * PERM_ESCRATCH when the order needs more workspace than the array holds
+ * (n > 53).  Every call on a GPU shares that GPU's array: calls that overlap
+ * on one GPU (on different streams, or from several threads) race and must
+ * be ordered by the caller.  The array keeps the last call's contents; no
+ * call relies on it starting at zero.  The first call on a device looks up
+ * the array's address there (no allocation).
+ */
+int perm_dense_f64_noalloc(int n, const double *A, int64_t lda, double *out, void *stream);
+
+/* Size in bytes of each GPU's fixed array used by perm_dense_f64_noalloc. */
+size_t perm_noalloc_scratch_bytes(void);
 
 /* Options of perm_dense_f64_ex (zero-initialise for the defaults). */
 /* Lane accumulation modes (Section 5, Table 3); block and grid partials are

@@ -19,6 +19,7 @@ PERM_EWORKSPACE = -3
 PERM_EHIP = -4
 PERM_EUNSUPPORTED = -5
 PERM_ECOMPILE = -6
+PERM_ESCRATCH = -7
 
 KIND_DENSE_F64 = 1
 KIND_DENSE_C128 = 2
@@ -41,6 +42,8 @@ SIGNATURES = [
     ("perm_workspace_bytes", _sz, [_int, _int, _i64]),
     ("perm_dense_f64", _int, [_int, _vp, _i64, _vp, _vp, _sz, _vp]),
     ("perm_dense_f64_ex", _int, [_int, _vp, _i64, _vp, _vp, _vp, _sz, _vp]),
+    ("perm_dense_f64_noalloc", _int, [_int, _vp, _i64, _vp, _vp]),
+    ("perm_noalloc_scratch_bytes", _sz, []),
     ("perm_dense_f64_launches", _i64, [_int, _vp]),
     ("perm_dense_c128", _int, [_int, _vp, _i64, _vp, _vp, _sz, _vp]),
     ("perm_sparse_f64", _int, [_int, _vp, _vp, _vp, _i32, _vp, _vp, _sz, _vp]),

@@ -195,6 +195,7 @@ const char *perm_strerror(int status)
     case PERM_EHIP: return "HIP runtime error";
     case PERM_EUNSUPPORTED: return "unsupported request";
     case PERM_ECOMPILE: return "run-time compilation of a generated kernel failed";
+    case PERM_ESCRATCH: return "request exceeds the fixed scratch of an allocation-free entry point";
     default: return "unknown status";
     }
 }
