@@ -62,6 +62,11 @@ def traffic_bytes():
     return TRAFFIC_BYTES_PER_LAUNCH if ok else None
 
 
+def _json(rec) -> str:
+    """One JSON line; numpy scalars become plain numbers and booleans."""
+    return json.dumps(rec, default=lambda o: o.item() if hasattr(o, "item") else str(o))
+
+
 def _golden(name):
     with open(os.path.join(GOLDEN, name)) as f:
         return json.load(f)
@@ -151,7 +156,8 @@ def _graph_ms(fn, reps=3):
     return ms
 
 
-def bench_batched(reps: int = 5, use_graph: bool = True, baselines: bool = True):
+def bench_batched(reps: int = 5, use_graph: bool = True, baselines: bool = True,
+                  autotune: bool = True):
     """Batched perm + dperm/dA of the 4096-matrix photon-counting batch (one
     hipGraph launch) against per-matrix launches, each side's device time:
     perm_grad on every matrix (all 4096 calls captured in one graph), and the
@@ -169,7 +175,7 @@ def bench_batched(reps: int = 5, use_graph: bool = True, baselines: bool = True)
     d = torch.from_numpy(data).to(dev)
     plan = api.BatchedPlan(ks, offs, want_grad=True)
     try:
-        tuned_ms = plan.autotune(d)
+        tuned_ms = plan.autotune(d) if autotune else None
         out, grad = plan.outputs(d)
         stream = torch.cuda.current_stream(dev)
         for _ in range(2):
@@ -331,7 +337,7 @@ def measure_rows():
         "subset_steps_per_s": 2 ** (n - 1) / (ms * 1e-3),
         "issue_slot_utilisation": ops / (ms * 1e-3) / LANE_OPS_PER_S,
         "abs_err": err, "tol": min(1e-13 * g["abs_sum"], 1e-10 * g["abs_perm"]),
-        "ok": err <= 1e-13 * g["abs_sum"] and err <= 1e-10 * g["abs_perm"]}
+        "ok": bool(err <= 1e-13 * g["abs_sum"] and err <= 1e-10 * g["abs_perm"])}
 
     # a9: exact binary, 32x32 Bernoulli and the 40x40 sparse pattern
     for name, key, a01 in (("a9_binary32", "bernoulli32", workloads.bernoulli(32, workloads.SEED_BERNOULLI32)),
@@ -352,7 +358,7 @@ def measure_rows():
             dt = time.perf_counter() - t0
             torch.cuda.synchronize()
             rec[label] = {"seconds": dt, "gpu_seconds": e0.elapsed_time(e1) * 1e-3,
-                          "first_call_seconds": first, "exact": str(val) == g["value"]}
+                          "first_call_seconds": first, "exact": bool(str(val) == g["value"])}
         rows[name] = rec
 
     # a8: sparse real, the 40x40 pattern with U[0,1) values (stored oracle
@@ -384,7 +390,7 @@ def measure_rows():
         "workload": f"40x40 pattern with 6 per row (seed 16582), values {values}; "
                     "perm_sparse_f64 (kernel generated for the pattern)",
         "ms": ms, "first_call_seconds": first, "subset_steps_per_s": 2 ** (n - 1) / (ms * 1e-3),
-        "rel_err": rel, "tol": 1e-10, "ok": rel <= 1e-10,
+        "rel_err": rel, "tol": 1e-10, "ok": bool(rel <= 1e-10),
         "staged_ms": ms_staged, "staged_rel_err": rel_staged}
 
     # a10: perm + dperm/dA of one 24x24 matrix (complex and real)
@@ -415,7 +421,7 @@ def measure_rows():
                       "issue_slot_utilisation": ops * 2 ** (n - 1) / (ms * 1e-3) / LANE_OPS_PER_S,
                       "perm_err_over_tol": perr, "minor_err_over_tol": merr,
                       "tol": "perm 1e-13 R(A); minors 1e-10 perm(|minor|)",
-                      "ok": perr <= 1.0 and merr <= 1.0}
+                      "ok": bool(perr <= 1.0 and merr <= 1.0)}
     return rows
 
 
@@ -426,7 +432,7 @@ def bench_rows():
     from paper_2502_16577_amd import api, workloads
 
     for name, rec in measure_rows().items():
-        print(json.dumps({"row": name, **rec}), flush=True)
+        print(_json({"row": name, **rec}), flush=True)
     n = 40
     a = workloads.sparse_rows(n, 6, workloads.SEED_SPARSE40)
     cp, ri, va = workloads.to_csc(a)
@@ -435,7 +441,7 @@ def bench_rows():
     t0 = time.perf_counter()
     v = api.perm_sparse_decomp(n, cp, ri, va).item()
     dt = time.perf_counter() - t0
-    print(json.dumps({"row": "next-3 DecompRyser", "workload": "40x40 0/1, 6 per row (seed 16582): "
+    print(_json({"row": "next-3 DecompRyser", "workload": "40x40 0/1, 6 per row (seed 16582): "
                       "DM pruning + Forbert-Marx, leaves batched on the GPU (host decomposition "
                       "included)", "seconds": dt, "perm": v}), flush=True)
 
@@ -466,7 +472,7 @@ def _perm_long(api, A, acc, label):
         api.perm_dense_f64_ex(A, accumulation=acc, first_launch=first, launch_count=group,
                               out=out, ws=ws)
         v = out.item()
-        print(json.dumps({"progress": label, "n": n, "launches_done": min(first + group, nl),
+        print(_json({"progress": label, "n": n, "launches_done": min(first + group, nl),
                           "launches": nl, "seconds": time.perf_counter() - t0}), flush=True)
     return v
 
@@ -490,7 +496,7 @@ def paper_tables(sizes):
         t0 = time.perf_counter()
         v = _perm_long(api, A, api.ACC_TWOSUM, f"table 4, n = {n}")
         dt = time.perf_counter() - t0
-        print(json.dumps({"table": 4, "n": n, "workload": f"dense {n}x{n} U[0,1) seed {1000 + n}",
+        print(_json({"table": 4, "n": n, "workload": f"dense {n}x{n} U[0,1) seed {1000 + n}",
                           "seconds": dt, "subset_steps_per_s": 2 ** (n - 1) / dt, "perm": v,
                           "paper_gv100_s": PAPER_TABLE4_GV100_S.get(n),
                           "paper_cpu44_s": PAPER_TABLE4_CPU44_S.get(n)}), flush=True)
@@ -505,7 +511,7 @@ def paper_tables(sizes):
             t0 = time.perf_counter()
             v = _perm_long(api, J, acc, f"table 3, n = {n}, {name}")
             dt = time.perf_counter() - t0
-            print(json.dumps({"table": 3, "n": n, "accumulation": name,
+            print(_json({"table": 3, "n": n, "accumulation": name,
                               "workload": f"all entries 0.91, {n}x{n}",
                               "rel_error": abs(v - exact) / exact, "seconds": dt,
                               "paper_gv100": PAPER_TABLE3_GV100.get(n)}), flush=True)
@@ -528,6 +534,8 @@ def main():
     ap.add_argument("--batched-eager", action="store_true",
                     help="launch the batched leg's kernels directly instead of as a hipGraph "
                          "(for counter collection, which does not follow graph launches)")
+    ap.add_argument("--batched-no-tune", action="store_true",
+                    help="batched leg with the default plan (no autotuning; profiling runs)")
     ap.add_argument("--batched-quick", action="store_true",
                     help="batched leg without the per-matrix baselines (profiling runs)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -542,7 +550,7 @@ def main():
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_read_per_launch": nbytes,
+        print(_json({"copy_bytes_read_per_launch": nbytes,
                           "copy_bytes_written_per_launch": nbytes, "launches": 3}))
         return
     if args.paper_tables:
@@ -552,8 +560,9 @@ def main():
         bench_rows()
         return
     if args.only_batched:
-        print(json.dumps(bench_batched(use_graph=not args.batched_eager,
-                                       baselines=not args.batched_quick)), flush=True)
+        print(_json(bench_batched(use_graph=not args.batched_eager,
+                                       baselines=not args.batched_quick,
+                                       autotune=not args.batched_no_tune)), flush=True)
         return
     if args.gpus != 1:
         print("bench.py: one GPU only (the library has no multi-GPU path); use --gpus 1",
@@ -624,7 +633,7 @@ def main():
         rec["batched"] = bench_batched()
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(a)
-    print(json.dumps(rec), flush=True)
+    print(_json(rec), flush=True)
 
 
 if __name__ == "__main__":

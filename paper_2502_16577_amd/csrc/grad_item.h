@@ -37,6 +37,8 @@
 // padding row keeps x = 1 and changes no product.
 #pragma once
 
+#include <type_traits>
+
 #include "sweep_common.h"
 
 namespace perm {
@@ -84,7 +86,7 @@ struct GradItemShape {
 // subsets are 64 w .. 64 w + 63); log2 chunk c >= 1; log2 re-seed interval
 // r <= c - 1; lanes_active (subsets K >= lanes_active idle with x = 0).
 // Outputs: perm_out[0..1] (double-double re, im of the item's share of
-// sum_g (-1)^g prod x, written by wave 0), and, if want_grad,
+// sum_g (-1)^g prod x; im is 0 for real matrices), and, if want_grad,
 // g_out[(i*N + j)*W + comp] for i < N (double-double share of
 // sum_g (-1)^g L_i tau_j; each wave zeroes and fills its own rows).
 template <int N, bool CPLX>
@@ -130,7 +132,7 @@ __device__ __forceinline__ void grad_item(const double *__restrict__ acol,
         const int rows = N - row0 < R ? N - row0 : R;
         for (int e = int(lane); e < rows * N * W; e += kWave) g_out[row0 * N * W + e] = dd{0.0, 0.0};
     }
-    double sr = 0.0, er = 0.0, si = 0.0, ei = 0.0;
+    double sr = 0.0, er = 0.0;  // this wave's compensated share of the permanent's sum
 
     auto reseed = [&](uint32_t l) {
         const uint64_t g = (Kl << c) | l;
@@ -168,40 +170,48 @@ __device__ __forceinline__ void grad_item(const double *__restrict__ acol,
         return (((g ^ (g >> 1)) >> j) & 1u) ? 1.0 : -1.0;
     };
 
-    auto step = [&](uint32_t l) {
-        const double sg = (l & 1u) ? -1.0 : 1.0;  // (-1)^g = (-1)^l
-        // Leave-one-out products of the slice in NB interleaved row blocks
-        // (independent dependency chains): pass 1 forms prefix products
-        // inside each block and the block products P_b; E_b = product of the
-        // other blocks and of the other slice, times the sign; pass 2 runs the
-        // suffix inside each block from E_b, so L_i = prefix_i E_b suffix_i.
+    // One step of the walk: the leave-one-out products of this slice's rows,
+    // their window sums, and the low columns' contribution.  NEG is the sign
+    // (-1)^g of the step (the walk takes steps in pairs, even then odd, so
+    // it is known at compile time).
+    //
+    // Rows are cut into NB blocks (independent dependency chains).  With
+    // pre_i the product of the earlier rows of i's block, P_b the product of
+    // block b, Q_b = P_0 ... P_{b-1}, F = P_0 ... P_{NB-1} the slice product
+    // and O the other slice's product, L_i = (-1)^g O (prod of the other
+    // blocks) pre_i (prod of the later rows of i's block).  The empty
+    // products (pre of a block's first row, Q_0) are never multiplied in:
+    // 3 (R - 1) complex products per lane and step in all.
+    auto step = [&](uint32_t l, auto neg_tag) {
+        constexpr bool NEG = decltype(neg_tag)::value;
+        // block b holds rows [b R / NB, (b + 1) R / NB): every block non-empty
         constexpr int NB = R >= 8 ? 4 : (R >= 4 ? 2 : 1);
-        constexpr int BS = (R + NB - 1) / NB;
-        double pr[R], pim[R];
-        double br[NB], bi[NB];
+        auto beg = [](int b) { return b * R / NB; };
+        double pr[R], pim[R];      // pre_i (unused for a block's first row)
+        double Pr[NB], Pi[NB];     // running block products, then P_b
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-            br[b] = 1.0;
-            bi[b] = 0.0;
+            Pr[b] = xr[beg(b)];
+            Pi[b] = xi[beg(b)];
         }
 #pragma unroll
-        for (int t = 0; t < BS; ++t)
+        for (int t = 1; t < (R + NB - 1) / NB; ++t)
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
-                const int i = b * BS + t;
-                if (i < R) {
-                    pr[i] = br[b];
-                    pim[i] = bi[b];
-                    gmul<CPLX>(br[b], bi[b], xr[i], xi[i]);
+                const int i = beg(b) + t;
+                if (i < beg(b + 1)) {
+                    pr[i] = Pr[b];
+                    pim[i] = Pi[b];
+                    gmul<CPLX>(Pr[b], Pi[b], xr[i], xi[i]);
                 }
             }
-        double er_[NB], ei_[NB];    // E_b
-        double fr = 1.0, fi = 0.0;  // prefix over blocks; ends as the slice product
+        double Qr[NB], Qi[NB];     // Q_b for b >= 1
+        double fr = Pr[0], fi = Pi[0];
 #pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            er_[b] = fr;
-            ei_[b] = fi;
-            gmul<CPLX>(fr, fi, br[b], bi[b]);
+        for (int b = 1; b < NB; ++b) {
+            Qr[b] = fr;
+            Qi[b] = fi;
+            gmul<CPLX>(fr, fi, Pr[b], Pi[b]);
         }
         // the other slices' products, through LDS (the buffer alternates
         // with the step parity, so one barrier per step suffices)
@@ -223,38 +233,52 @@ __device__ __forceinline__ void grad_item(const double *__restrict__ acol,
                 gmul<CPLX>(orr, oii, xo[0], CPLX ? xo[1] : 0.0);
             }
         }
-        if (h == 0) {  // the whole product, counted once per item
-            double pr0 = fr, pi0 = fi;
-            gmul<CPLX>(pr0, pi0, orr, oii);
-            acc_add(sr, er, sg * pr0);
-            if (CPLX) acc_add(si, ei, sg * pi0);
+        if (NEG) {
+            orr = -orr;
+            oii = -oii;
+        }
+        // the whole signed product, shared between the waves: for complex
+        // matrices wave 0 accumulates its real part and wave 1 its imaginary
+        // part; for real ones wave 0 takes the even steps and wave 1 the odd
+        if constexpr (CPLX) {
+            if (h == 0) acc_add(sr, er, fr * orr - fi * oii);
+            else acc_add(sr, er, fr * oii + fi * orr);
+        } else {
+            if (h == (NEG ? 1 : 0)) acc_add(sr, er, fr * orr);
         }
         if (!want_grad) return;
+        // E_b = (-1)^g O prod_{b' != b} P_b', formed from the last block down
+        double Er[NB], Ei[NB];
         {
-            double gr = sg * orr, gi = sg * oii;  // suffix over blocks, with the sign
+            double tr = orr, ti = oii;
 #pragma unroll
-            for (int b = NB - 1; b >= 0; --b) {
-                gmul<CPLX>(er_[b], ei_[b], gr, gi);
-                gmul<CPLX>(gr, gi, br[b], bi[b]);
+            for (int b = NB - 1; b >= 1; --b) {
+                Er[b] = Qr[b];
+                Ei[b] = Qi[b];
+                gmul<CPLX>(Er[b], Ei[b], tr, ti);
+                gmul<CPLX>(tr, ti, Pr[b], Pi[b]);
             }
+            Er[0] = tr;
+            Ei[0] = ti;
         }
+        // within each block from its last row: L_i = pre_i E_b (later rows)
         double *vr = vbuf + lane * STRIDE;
         double *vi = vbuf + (W - 1) * kWave * STRIDE + lane * STRIDE;
 #pragma unroll
-        for (int t = BS - 1; t >= 0; --t)
+        for (int t = (R + NB - 1) / NB - 1; t >= 0; --t)
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
-                const int i = b * BS + t;
-                if (i < R) {
-                    double lr = pr[i], li = pim[i];
-                    gmul<CPLX>(lr, li, er_[b], ei_[b]);
+                const int i = beg(b) + t;
+                if (i < beg(b + 1)) {
+                    double lr = Er[b], li = Ei[b];
+                    if (t > 0) {
+                        gmul<CPLX>(lr, li, pr[i], pim[i]);
+                        gmul<CPLX>(Er[b], Ei[b], xr[i], xi[i]);
+                    }
                     wr[i] += lr;
                     if (CPLX) wi[i] += li;
-                    if (f > 0) {
-                        vr[i] = lr;
-                        if (CPLX) vi[i] = li;
-                    }
-                    gmul<CPLX>(er_[b], ei_[b], xr[i], xi[i]);
+                    vr[i] = lr;
+                    if (CPLX) vi[i] = li;
                 }
             }
         if (f == 0) return;
@@ -267,16 +291,20 @@ __device__ __forceinline__ void grad_item(const double *__restrict__ acol,
         for (int q = 0; q < W; ++q) {
             double s = 0.0;
             if (jj < R) {
+                // reads are issued eight at a time before their adds, so the
+                // LDS latency is paid twice per component rather than per read
                 const double *col = vbuf + q * kWave * STRIDE + jj + 16 * kq * STRIDE;
-                double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
 #pragma unroll
-                for (int rr = 0; rr < 16; rr += 4) {
-                    s0 += col[rr * STRIDE];
-                    s1 += col[(rr + 1) * STRIDE];
-                    s2 += col[(rr + 2) * STRIDE];
-                    s3 += col[(rr + 3) * STRIDE];
+                for (int half = 0; half < 2; ++half) {
+                    double v[8];
+#pragma unroll
+                    for (int rr = 0; rr < 8; ++rr) v[rr] = col[(8 * half + rr) * STRIDE];
+#pragma unroll
+                    for (int span = 4; span >= 1; span /= 2)
+#pragma unroll
+                        for (int rr = 0; rr < span; ++rr) v[rr] += v[rr + span];
+                    s = half ? s + v[0] : v[0];
                 }
-                s = (s0 + s1) + (s2 + s3);
             }
             acc_lo[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(s, bl, acc_lo[q], 0, 0, 0);
         }
@@ -353,7 +381,7 @@ __device__ __forceinline__ void grad_item(const double *__restrict__ acol,
             const int j = __builtin_ctz(l);
             flip(j, (((l ^ (l >> 1)) >> j) & 1u) != 0u);
         }
-        step(l);
+        step(l, std::false_type{});
         if (want_grad && f == 0) close_window(l);
         if (c == 1) {
             reseed(l + 1);  // the column-0 sign depends on the lane when c == 1
@@ -361,15 +389,25 @@ __device__ __forceinline__ void grad_item(const double *__restrict__ acol,
             const uint32_t l1 = l + 1;
             flip(0, ((l1 ^ (l1 >> 1)) & 1u) != 0u);
         }
-        step(l + 1);
+        step(l + 1, std::true_type{});
         if (want_grad && ((l + 2) & fmask) == 0) close_window((l + 1) & ~fmask);
     }
-    if (h == 0) {
-        const dd pr = wave_reduce_dd(dd{sr, er});
-        const dd pi = wave_reduce_dd(dd{si, ei});
-        if (lane == 0) {
-            perm_out[0] = pr;
-            perm_out[1] = pi;
+    // the item's share of sum_g (-1)^g prod x: for complex matrices each
+    // wave holds one component; for real ones both hold parts of the real
+    // sum, combined through LDS
+    const dd part = wave_reduce_dd(dd{sr, er});
+    if constexpr (CPLX) {
+        if (lane == 0) perm_out[h] = part;
+    } else {
+        __syncthreads();  // every wave is done with the exchange buffers
+        if (h == 1 && lane == 0) {
+            xbuf[0] = part.hi;
+            xbuf[1] = part.lo;
+        }
+        __syncthreads();
+        if (h == 0 && lane == 0) {
+            perm_out[0] = dd_add(part, dd{xbuf[0], xbuf[1]});
+            perm_out[1] = dd{0.0, 0.0};
         }
     }
 }

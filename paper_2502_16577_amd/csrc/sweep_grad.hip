@@ -54,12 +54,11 @@ __global__ __launch_bounds__(kBlock) void prep_grad(int n, int np, const double 
 // (subsets 64 w .. 64 w + 63).  perm_part[2w..2w+1] and g_part[w * W*N*N ...]
 // receive the item's shares.
 template <int N, bool CPLX>
-__global__ __launch_bounds__(kGradBlock) void sweep_grad(const double *__restrict__ acol,
-                                                         const double *__restrict__ aneg,
-                                                         const double *__restrict__ x0,
-                                                         dd *__restrict__ perm_part,
-                                                         dd *__restrict__ g_part, int c, int r,
-                                                         int64_t lanes_active, int want_grad)
+__device__ __forceinline__ void sweep_grad_body(const double *__restrict__ acol,
+                                                const double *__restrict__ aneg,
+                                                const double *__restrict__ x0,
+                                                dd *__restrict__ perm_part, dd *__restrict__ g_part,
+                                                int c, int r, int64_t lanes_active, int want_grad)
 {
     using S = GradItemShape<N, CPLX>;
     static_assert(S::THREADS == kGradBlock, "block shape");
@@ -67,6 +66,27 @@ __global__ __launch_bounds__(kGradBlock) void sweep_grad(const double *__restric
     const uint64_t w = blockIdx.x;
     grad_item<N, CPLX>(acol, aneg, x0, w, c, r, uint64_t(lanes_active), perm_part + 2 * w,
                        g_part + w * uint64_t(S::W * N * N), want_grad != 0, lds);
+}
+
+// Orders up to 24 fit two waves per SIMD (at most 256 registers per lane,
+// as in the batched kernel of orders 17..24); the compiler is held to that.
+template <int N, bool CPLX>
+__global__ __launch_bounds__(kGradBlock) __attribute__((amdgpu_waves_per_eu(2))) void
+sweep_grad(const double *__restrict__ acol, const double *__restrict__ aneg,
+           const double *__restrict__ x0, dd *__restrict__ perm_part, dd *__restrict__ g_part, int c,
+           int r, int64_t lanes_active, int want_grad)
+{
+    sweep_grad_body<N, CPLX>(acol, aneg, x0, perm_part, g_part, c, r, lanes_active, want_grad);
+}
+
+// Orders 25..32: one wave per SIMD.
+template <int N, bool CPLX>
+__global__ __launch_bounds__(kGradBlock) void sweep_grad_large(
+    const double *__restrict__ acol, const double *__restrict__ aneg, const double *__restrict__ x0,
+    dd *__restrict__ perm_part, dd *__restrict__ g_part, int c, int r, int64_t lanes_active,
+    int want_grad)
+{
+    sweep_grad_body<N, CPLX>(acol, aneg, x0, perm_part, g_part, c, r, lanes_active, want_grad);
 }
 
 // n = 1: perm = a, dperm/da = 1.
@@ -132,9 +152,14 @@ static void launch_grad_n(const GradPlan &p, const double *acol, const double *a
                           const double *x0, dd *pp, dd *gp, bool want_grad, double *out_perm,
                           double *out_grad, hipStream_t stream)
 {
-    hipLaunchKernelGGL((sweep_grad<N, CPLX>), dim3(unsigned(p.waves)), dim3(kGradBlock), 0, stream,
-                       acol, aneg, x0, pp, gp, p.log2_chunk, p.log2_reseed, p.lanes_active,
-                       int(want_grad));
+    if constexpr (N <= 24)
+        hipLaunchKernelGGL((sweep_grad<N, CPLX>), dim3(unsigned(p.waves)), dim3(kGradBlock), 0,
+                           stream, acol, aneg, x0, pp, gp, p.log2_chunk, p.log2_reseed,
+                           p.lanes_active, int(want_grad));
+    else
+        hipLaunchKernelGGL((sweep_grad_large<N, CPLX>), dim3(unsigned(p.waves)), dim3(kGradBlock),
+                           0, stream, acol, aneg, x0, pp, gp, p.log2_chunk, p.log2_reseed,
+                           p.lanes_active, int(want_grad));
     if (want_grad)
         hipLaunchKernelGGL((finalize_grad<N, CPLX>), dim3(unsigned(N * N * (CPLX ? 2 : 1))),
                            dim3(kBlock), 0, stream, pp, gp, p.waves, out_perm, out_grad);
