@@ -61,6 +61,9 @@ def _declare(lib):
         f.argtypes = [c_int, dp, c_int, dp, dp]
     lib.orc_ryser_real_sample.restype = c_int
     lib.orc_ryser_real_sample.argtypes = [c_int, dp, c_int, ctypes.c_uint64, ctypes.c_uint64, dp]
+    lib.orc_ryser_real_part.restype = c_int
+    lib.orc_ryser_real_part.argtypes = [c_int, dp, i32p, i32p, dp, c_int, ctypes.c_uint64,
+                                        ctypes.c_uint64, dp, dp]
     lib.orc_ryser_csc_real.restype = c_int
     lib.orc_ryser_csc_real.argtypes = [c_int, i32p, i32p, dp, c_int, dp, dp]
     lib.orc_ryser_binary.restype = c_int
@@ -181,6 +184,32 @@ class Oracle:
         return float(out[0] + out[1])
 
     CHUNK_STEPS = 4096
+
+    def ryser_part(self, a, part: int, nparts: int, threads: int = 0, csc=None):
+        """Part ``part`` of ``nparts`` of Algorithm 1's unscaled sum for a
+        real matrix (dense ``a``, or ``csc = (col_ptr, row_idx, vals)`` with
+        ``a`` the order n): the walk's chunks split into equal consecutive
+        ranges, the g = 0 term in part 0.  Returns ((hi, lo), (abs_hi, abs_lo));
+        the permanent is 2 (-1)^(n-1) times the sum over all parts."""
+        out = np.zeros(2)
+        absum = np.zeros(2)
+        i32 = ctypes.POINTER(ctypes.c_int32)
+        if csc is None:
+            r = _real(a)
+            n = r.shape[0]
+            rc = self.lib.orc_ryser_real_part(n, _dptr(r), None, None, None, threads, part, nparts,
+                                              _dptr(out), _dptr(absum))
+        else:
+            n = int(a)
+            cp = np.ascontiguousarray(csc[0], dtype=np.int32)
+            ri = np.ascontiguousarray(csc[1], dtype=np.int32)
+            v = np.ascontiguousarray(csc[2], dtype=np.float64)
+            if cp.size != n + 1 or ri.size != v.size:
+                raise ValueError("malformed CSC")
+            rc = self.lib.orc_ryser_real_part(n, None, cp.ctypes.data_as(i32), ri.ctypes.data_as(i32),
+                                              _dptr(v), threads, part, nparts, _dptr(out), _dptr(absum))
+        _check(rc, "ryser_real_part")
+        return (float(out[0]), float(out[1])), (float(absum[0]), float(absum[1]))
 
     # -- Algorithm 2 ----------------------------------------------------------
     def ryser_csc(self, n: int, col_ptr, row_idx, vals, threads: int = 0,

@@ -521,6 +521,88 @@ int orc_ryser_real_sample(int n, const double *a, int nthreads, uint64_t first_c
     return 0;
 }
 
+/* Part `part` of `nparts` of the unscaled sum of Algorithm 1 for a real
+ * matrix, dense (a) or given by CSC columns (col_ptr, row_idx, vals; a is
+ * NULL then): the chunks [part*K/nparts, (part+1)*K/nparts) of the walk's
+ * K chunks, plus the g = 0 term in part 0.  Written as a (hi, lo) pair, with
+ * the part's share of sum_g |term_g| in absum.  The sum of all parts times
+ * 2 (-1)^(n-1) is the permanent (the whole walk, grouped differently), so a
+ * long sweep can be computed piece by piece and resumed. */
+int orc_ryser_real_part(int n, const double *a, const int32_t *col_ptr,
+                        const int32_t *row_idx, const double *vals, int nthreads,
+                        uint64_t part, uint64_t nparts, double out[2], double absum[2])
+{
+    if (n < 2 || n > 63 || (!a && !col_ptr) || !out || !absum || nparts == 0 || part >= nparts)
+        return -1;
+    ld x0r[64], x0i[64];
+    for (int i = 0; i < n; i++) { x0r[i] = 0; x0i[i] = 0; }
+    if (a) {
+        for (int i = 0; i < n; i++) {
+            ld sr = 0;
+            for (int j = 0; j < n; j++) sr += a[i * n + j];
+            x0r[i] = a[i * n + n - 1] - sr / 2;
+        }
+    } else {
+        /* row sums and last-column entries from the stored nonzeros */
+        ld rsum[64], last[64];
+        for (int i = 0; i < n; i++) { rsum[i] = 0; last[i] = 0; }
+        if (col_ptr[0] != 0) return -1;
+        for (int j = 0; j < n; j++) {
+            if (col_ptr[j + 1] < col_ptr[j]) return -1;
+            for (int32_t q = col_ptr[j]; q < col_ptr[j + 1]; q++) {
+                if (row_idx[q] < 0 || row_idx[q] >= n) return -1;
+                rsum[row_idx[q]] += vals[q];
+                if (j == n - 1) last[row_idx[q]] = vals[q];
+            }
+        }
+        for (int i = 0; i < n; i++) x0r[i] = last[i] - rsum[i] / 2;
+    }
+    ryser_job_t J;
+    memset(&J, 0, sizeof J);
+    J.n = n; J.cplx = 0; J.a = a; J.x0r = x0r; J.x0i = x0i;
+    if (!a) { J.csc_ptr = col_ptr; J.csc_row = row_idx; J.csc_val = vals; }
+    J.steps = (1ull << (n - 1)) - 1;
+    const uint64_t total_chunks = (J.steps + ORC_CHUNK - 1) / ORC_CHUNK;
+    /* part boundaries by 128-bit products, so any nparts is exact */
+    const uint64_t c0 = (uint64_t)(((unsigned __int128)total_chunks * part) / nparts);
+    const uint64_t c1 = (uint64_t)(((unsigned __int128)total_chunks * (part + 1)) / nparts);
+    const uint64_t nchunks = c1 - c0;
+    J.chunks_per_item = 1;
+    J.nitems = nchunks;
+    J.first_chunk = c0;
+    size_t nb = (nchunks ? nchunks : 1) * sizeof(ld);
+    J.item_re = (ld *)calloc(1, nb);
+    J.item_im = (ld *)calloc(1, nb);
+    J.item_abs = (ld *)calloc(1, nb);
+    if (!J.item_re || !J.item_im || !J.item_abs) {
+        free(J.item_re); free(J.item_im); free(J.item_abs);
+        return -1;
+    }
+    int T = default_threads(nthreads);
+    if (T > 256) T = 256;
+    pthread_t th[256];
+    int ok[256] = {0};
+    for (int t = 1; t < T; t++) ok[t] = pthread_create(&th[t], NULL, ryser_worker, &J) == 0;
+    ryser_worker(&J);
+    for (int t = 1; t < T; t++) if (ok[t]) pthread_join(th[t], NULL);
+    kahan_t k = {0, 0};
+    ld abs_sum = 0;
+    if (part == 0) {
+        ld p0 = 1;
+        for (int i = 0; i < n; i++) p0 *= x0r[i];
+        kahan_add(&k, p0);
+        abs_sum += p0 < 0 ? -p0 : p0;
+    }
+    for (uint64_t it = 0; it < J.nitems; it++) {
+        kahan_add(&k, J.item_re[it]);
+        abs_sum += J.item_abs[it];
+    }
+    free(J.item_re); free(J.item_im); free(J.item_abs);
+    ld_split(k.s - k.c, out);
+    ld_split(abs_sum, absum);
+    return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Algorithm 2 (SpaRyser): the walk on CSC columns                          */
 /* ------------------------------------------------------------------------ */

@@ -195,6 +195,36 @@ def test_csc_walk_closed_forms(oracle):
             math.factorial(3) ** (n // 3) * math.factorial(n % 3))) < 1e-14
 
 
+def test_walk_in_parts_adds_up_to_the_whole(oracle):
+    # the walk cut into consecutive pieces (how the 40 x 40 reference values
+    # are computed) sums to the permanent: checked against Eq. (1), the
+    # closed forms n! and D_n, and the undivided walk, dense and CSC
+    from fractions import Fraction
+
+    def whole(n, parts):
+        tot = sum(Fraction(h) + Fraction(l) for (h, l), _ in parts) * (2 if n % 2 else -2)
+        ab = 2 * sum(Fraction(h) + Fraction(l) for _, (h, l) in parts)
+        return float(tot), float(ab)
+
+    for n in (2, 5, 8):
+        a = W.uniform(n, 300 + n) - 0.5
+        v, _ = whole(n, [oracle.ryser_part(a, p, 3) for p in range(3)])
+        assert rel(v, oracle.brute(a)) < 1e-13
+    for n, k in ((12, 1), (13, 4), (16, 9)):
+        v, r = whole(n, [oracle.ryser_part(W.all_ones(n), p, k) for p in range(k)])
+        assert v == math.factorial(n) and rel(r, r_all_ones(n)) < 1e-14
+        v, _ = whole(n, [oracle.ryser_part(W.ones_minus_identity(n), p, k) for p in range(k)])
+        assert rel(v, derangements(n)) < 1e-15
+    a = W.uniform(17, 317)
+    want, r = oracle.ryser(a, with_abs=True)
+    v, rp = whole(17, [oracle.ryser_part(a, p, 7) for p in range(7)])
+    assert rel(v, want) < 1e-15 and rel(rp, r) < 1e-15
+    s = W.sparse_rows(18, 4, 318).astype(np.float64) * W.uniform(18, 319)
+    cp, ri, vals = W.to_csc(s)
+    v, _ = whole(18, [oracle.ryser_part(18, p, 5, csc=(cp, ri, vals)) for p in range(5)])
+    assert rel(v, oracle.ryser_csc(18, cp, ri, vals)) < 1e-15
+
+
 # --- R(A), the Ryser absolute sum 2 sum_g |prod_i x_i(g)| ---------------------
 # Closed forms that follow from Algorithm 1's start vector
 # x_i(S) = a_{i,n-1} + sum_{j in S} a_ij - r_i / 2 over the subsets S of the
