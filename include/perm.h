@@ -351,9 +351,15 @@ int perm_weighted_sum(int count, const double *weights, const perm_c128 *perms, 
  * with perm(A) = sum_m weight_m perm(leaf_m); a leaf of order 0 is stored as
  * the 1 x 1 matrix [1].  min_leaf stops decomposing matrices of that order or
  * less.  PERM_ERANGE if more than 2^22 leaves would be produced.
+ *   PERM_DECOMP_FOLD (with PERM_DECOMP_FM) keeps no leaf of order 0, 1 or 2:
+ *                   their weighted permanents (w, w a, w (ad + bc)) are summed
+ *                   on the host in double-double, and perm_decomp_folded
+ *                   returns that sum, so perm(A) = folded + sum_m weight_m
+ *                   perm(leaf_m).  Without the flag folded is 0.
  */
 #define PERM_DECOMP_DM 1
 #define PERM_DECOMP_FM 2
+#define PERM_DECOMP_FOLD 4
 
 typedef struct perm_decomp perm_decomp;
 
@@ -368,6 +374,8 @@ int perm_decomp_leaf(const perm_decomp *d, int idx, int *k, double *weight, doub
  * data = the leaves' row-major entries back to back (total_elements). */
 int perm_decomp_leaves(const perm_decomp *d, int32_t *k, double *weight, int64_t *offset,
                        double *data);
+/* The folded leaves' sum as a (hi, lo) double-double (host array of 2). */
+int perm_decomp_folded(const perm_decomp *d, double out[2]);
 void perm_decomp_destroy(perm_decomp *d);
 
 /* The k-th prime used by perm_binary_exact (k = 0..5; the six smallest

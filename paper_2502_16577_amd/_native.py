@@ -63,6 +63,7 @@ SIGNATURES = [
                                 ctypes.POINTER(_i64)]),
     ("perm_decomp_leaf", _int, [_vp, _int, ctypes.POINTER(_int), ctypes.POINTER(ctypes.c_double), _vp]),
     ("perm_decomp_leaves", _int, [_vp, _vp, _vp, _vp, _vp]),
+    ("perm_decomp_folded", _int, [_vp, _vp]),
     ("perm_decomp_destroy", None, [_vp]),
     ("perm_batched_plan_info", _int, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_int), _vp,
                                       ctypes.POINTER(_int)]),

@@ -352,11 +352,12 @@ class BatchedPlan:
 
 DECOMP_DM = 1
 DECOMP_FM = 2
+DECOMP_FOLD = 4
 
 
 def _decompose_arrays(n: int, col_ptr, row_idx, vals, flags: int, min_leaf: int):
     """perm_decompose + perm_decomp_leaves: (k int32[L], weight float64[L],
-    offset int64[L], data float64[total], removed)."""
+    offset int64[L], data float64[total], removed, folded (hi, lo))."""
     col_ptr = np.ascontiguousarray(col_ptr, dtype=np.int32)
     row_idx = np.ascontiguousarray(row_idx, dtype=np.int32)
     vals = np.ascontiguousarray(vals, dtype=np.float64)
@@ -377,7 +378,9 @@ def _decompose_arrays(n: int, col_ptr, row_idx, vals, flags: int, min_leaf: int)
         if cnt.value:
             N.check(L.perm_decomp_leaves(h, ks.ctypes.data, ws.ctypes.data, offs.ctypes.data,
                                          data.ctypes.data), "perm_decomp_leaves")
-        return ks, ws, offs, data, rem.value
+        folded = np.zeros(2, np.float64)
+        N.check(L.perm_decomp_folded(h, folded.ctypes.data), "perm_decomp_folded")
+        return ks, ws, offs, data, rem.value, folded
     finally:
         L.perm_decomp_destroy(h)
 
@@ -387,47 +390,62 @@ def decompose(n: int, col_ptr, row_idx, vals, flags: int = DECOMP_DM | DECOMP_FM
     """Section 4 preprocessing on the host (no GPU work).
 
     Returns (leaves, removed) with leaves = [(weight, k x k float64 array)]:
-    perm(A) = sum weight * perm(leaf); an empty list means perm = 0."""
-    ks, ws, offs, data, removed = _decompose_arrays(n, col_ptr, row_idx, vals, flags, min_leaf)
+    perm(A) = sum weight * perm(leaf); an empty list means perm = 0.  With
+    DECOMP_FOLD the leaves of order <= 2 are summed on the host and returned
+    as one leaf of order 0 per component of the double-double sum (weight
+    hi, then lo), so the identity still reads sum weight * perm(leaf)."""
+    ks, ws, offs, data, removed, folded = _decompose_arrays(n, col_ptr, row_idx, vals, flags,
+                                                            min_leaf)
     leaves = [(float(ws[i]), data[offs[i]:offs[i] + ks[i] * ks[i]].reshape(ks[i], ks[i]))
               for i in range(len(ks))]
+    if flags & DECOMP_FOLD:
+        leaves += [(float(f), np.zeros((0, 0))) for f in folded if f != 0.0]
     return leaves, removed
 
 
-def perm_sparse_decomp(n: int, col_ptr, row_idx, vals, flags: int = DECOMP_DM | DECOMP_FM,
-                       device="cuda:0"):
+def perm_sparse_decomp(n: int, col_ptr, row_idx, vals,
+                       flags: int = DECOMP_DM | DECOMP_FM | DECOMP_FOLD, device="cuda:0",
+                       dense_min: int = 20):
     """perm of a sparse real matrix by the Section 4 pipeline: host
-    decomposition into weighted leaves, one batched GPU launch over the
-    leaves, and a double-double weighted sum on the GPU.  Returns a 0-d
-    float64 device tensor."""
+    decomposition into weighted leaves (those of order <= 2 summed on the
+    host with DECOMP_FOLD); leaves of order >= dense_min each as one real
+    full-chip sweep (perm_dense_f64), the smaller ones in one batched launch;
+    then a double-double weighted sum on the GPU.  Returns a 0-d float64
+    device tensor."""
     device = torch.device(device)
-    ks, ws, offs, data, _ = _decompose_arrays(n, col_ptr, row_idx, vals, flags, 0)
+    ks, ws, offs, data, _, folded = _decompose_arrays(n, col_ptr, row_idx, vals, flags, 0)
     out = torch.zeros((), dtype=torch.complex128, device=device)
-    if len(ks) == 0:
+    # the folded sum enters the weighted sum as two order-0 leaves (perm 1)
+    fw = [float(f) for f in folded if f != 0.0]
+    if len(ks) == 0 and not fw:
         return out.real.clone()
-    small = np.nonzero(ks <= 32)[0]
-    big = np.nonzero(ks > 32)[0]
+    dense_min = max(2, min(int(dense_min), 33))
+    small = np.nonzero(ks < dense_min)[0]
+    big = np.nonzero(ks >= dense_min)[0]
     order = np.concatenate([small, big])
-    perms = torch.zeros(len(ks), dtype=torch.complex128, device=device)
+    perms = torch.zeros(len(ks) + len(fw), dtype=torch.complex128, device=device)
+    perms[len(ks):] = 1.0
     keep = []
     if len(small):
-        # the batched kernels take complex entries: every leaf's entries as
-        # complex, back to back as the decomposition returned them
-        d = torch.from_numpy(data).to(device).to(torch.complex128)
-        plan = BatchedPlan(ks[small], offs[small], want_grad=False, device=device)
+        # the batched kernels take complex entries: the small leaves' entries
+        # back to back
+        sizes = ks[small].astype(np.int64) ** 2
+        soff = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
+        packed = np.concatenate([data[offs[i]:offs[i] + sz] for i, sz in zip(small, sizes)])
+        d = torch.from_numpy(packed).to(device).to(torch.complex128)
+        plan = BatchedPlan(ks[small], soff, want_grad=False, device=device)
         plan.run(d, out=perms[:len(small)], use_graph=False)
         keep += [plan, d]
-    if len(big):  # orders above the batched limit: one dense launch each
+    if len(big):  # one real sweep over the whole chip per large leaf
+        dev = torch.from_numpy(data).to(device)
+        keep.append(dev)
         pv = perms.view(torch.float64)
         for t, i in enumerate(big):
             k = int(ks[i])
-            A = torch.from_numpy(np.ascontiguousarray(data[offs[i]:offs[i] + k * k].reshape(k, k)))
-            A = A.to(device)
-            perm_dense_f64(A, out=pv[2 * (len(small) + t)])
-            keep.append(A)
-    w = torch.from_numpy(np.ascontiguousarray(ws[order])).to(device)
-    N.check(N.lib().perm_weighted_sum(len(ks), w.data_ptr(), perms.data_ptr(), out.data_ptr(),
-                                      _stream(device)), "perm_weighted_sum")
+            perm_dense_f64(dev[offs[i]:offs[i] + k * k].view(k, k), out=pv[2 * (len(small) + t)])
+    w = torch.from_numpy(np.ascontiguousarray(np.concatenate([ws[order], fw]))).to(device)
+    N.check(N.lib().perm_weighted_sum(len(ks) + len(fw), w.data_ptr(), perms.data_ptr(),
+                                      out.data_ptr(), _stream(device)), "perm_weighted_sum")
     torch.cuda.current_stream(device).synchronize()  # keep plan / weights alive until done
     for obj in keep:
         if isinstance(obj, BatchedPlan):

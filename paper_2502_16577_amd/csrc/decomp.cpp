@@ -222,8 +222,29 @@ Mat zeroed_front(const Mat &A, const Front &F)
     return Z;
 }
 
+// Double-double accumulator for the folded leaves (two-sum of Ogita, Rump
+// and Oishi; products split exactly by FMA).
+struct DDSum {
+    double hi = 0.0, lo = 0.0;
+    void add(double v)
+    {
+        const double s = hi + v;
+        const double bb = s - hi;
+        lo += (hi - (s - bb)) + (v - bb);
+        hi = s;
+    }
+    void add_product(double a, double b)
+    {
+        const double p = a * b;
+        add(p);
+        add(std::fma(a, b, -p));
+    }
+};
+
 struct Decomposer {
     int min_leaf = 0;              // stop decomposing at this order
+    bool fold = false;             // sum leaves of order <= 2 into `folded`
+    DDSum folded;
     int64_t split_budget = 1 << 16;  // two-way splits (minNnz 3 or 4) allowed in total
     int64_t max_leaves = 1 << 22;
     std::vector<Leaf> leaves;
@@ -232,6 +253,17 @@ struct Decomposer {
     void rec(Mat A, double w, int depth)
     {
         if (overflow) return;
+        if (fold && A.n <= 2) {  // perm of order 0, 1, 2 directly: w, w a, w (ad + bc)
+            if (A.n == 0) {
+                folded.add(w);
+            } else if (A.n == 1) {
+                folded.add_product(w, A.a[0]);
+            } else {
+                folded.add_product(w * A.a[0], A.a[3]);
+                folded.add_product(w * A.a[1], A.a[2]);
+            }
+            return;
+        }
         if (A.n == 0) {  // the empty product: a 1 x 1 leaf [1] carries the weight
             Mat one;
             one.n = 1;
@@ -298,6 +330,7 @@ struct Decomposer {
 
 struct perm_decomp {
     std::vector<Leaf> leaves;
+    double folded[2] = {0.0, 0.0};  // sum of the folded leaves (hi, lo)
     int64_t removed = 0;
     int zero = 0;
 };
@@ -333,12 +366,15 @@ int perm_decompose(int n, const int32_t *col_ptr, const int32_t *row_idx, const 
     if (flags & PERM_DECOMP_FM) {
         Decomposer dec;
         dec.min_leaf = std::max(min_leaf, 0);
+        dec.fold = (flags & PERM_DECOMP_FOLD) != 0;
         dec.rec(A, 1.0, 0);
         if (dec.overflow) {
             delete D;
             return PERM_ERANGE;
         }
         D->leaves = std::move(dec.leaves);
+        D->folded[0] = dec.folded.hi + dec.folded.lo;
+        D->folded[1] = dec.folded.lo - (D->folded[0] - dec.folded.hi);
     } else {
         D->leaves.push_back(Leaf{1.0, A});
     }
@@ -387,6 +423,14 @@ int perm_decomp_leaves(const perm_decomp *d, int32_t *k, double *weight, int64_t
             std::memcpy(data + off, L.m.a.data(), L.m.a.size() * sizeof(double));
         off += int64_t(L.m.n) * L.m.n;
     }
+    return PERM_OK;
+}
+
+int perm_decomp_folded(const perm_decomp *d, double out[2])
+{
+    if (!d || !out) return PERM_EINVAL;
+    out[0] = d->folded[0];
+    out[1] = d->folded[1];
     return PERM_OK;
 }
 

@@ -164,6 +164,13 @@ def block_ones(n: int, b: int) -> np.ndarray:
     return a
 
 
+def scaling_vectors(n: int, seed: int):
+    """Two vectors d, e of n entries uniform in [0.5, 1.5) (row and column
+    scalings of a test pattern)."""
+    rng = np.random.default_rng(seed)
+    return rng.random(n) + 0.5, rng.random(n) + 0.5
+
+
 def to_csc(a):
     """CSC (col_ptr int32[n+1], row_idx int32[nnz], vals float64[nnz]) of a dense matrix."""
     a = np.asarray(a)

@@ -72,3 +72,33 @@ def test_decomposition_of_signed_values(oracle):
     leaves, _ = api.decompose(n, cp, ri, v)
     want, r = oracle.ryser(A, with_abs=True)
     assert abs(weighted(oracle, leaves) - want) <= 1e-12 * r
+
+
+@pytest.mark.parametrize("n,per_row,seed", [(12, 3, 2), (16, 3, 4), (18, 5, 5), (24, 4, 7)])
+def test_folded_leaves_preserve_perm(oracle, n, per_row, seed):
+    # leaves of order 0, 1 and 2 summed on the host (two order-0 leaves carry
+    # the double-double sum); no stored leaf of order <= 2 remains
+    pat = W.sparse_rows(n, per_row, seed).astype(np.float64)
+    A = pat * (np.random.default_rng(seed).random((n, n)) - 0.3)
+    cp, ri, v = W.to_csc(A)
+    want, r = oracle.ryser(A, with_abs=True)
+    plain, _ = api.decompose(n, cp, ri, v)
+    folded, _ = api.decompose(n, cp, ri, v, flags=api.DECOMP_DM | api.DECOMP_FM | api.DECOMP_FOLD)
+    assert all(m.shape[0] > 2 for w, m in folded if m.shape[0] != 0)
+    assert sum(1 for _, m in folded if m.shape[0] == 0) <= 2
+    assert len(folded) <= len(plain)
+    assert abs(weighted(oracle, folded) - want) <= 1e-11 * abs(want) + 1e-14 * r
+    assert abs(weighted(oracle, folded) - weighted(oracle, plain)) <= 1e-14 * r
+
+
+def test_folding_a_fully_reducible_matrix(oracle):
+    # a tridiagonal matrix reduces completely (every row has <= 3 nonzeros):
+    # with folding there are no stored leaves at all
+    n = 20
+    rng = np.random.default_rng(9)
+    A = np.diag(rng.random(n) + 0.5) + np.diag(rng.random(n - 1), 1) + np.diag(rng.random(n - 1), -1)
+    cp, ri, v = W.to_csc(A)
+    leaves, _ = api.decompose(n, cp, ri, v, flags=api.DECOMP_DM | api.DECOMP_FM | api.DECOMP_FOLD)
+    assert all(m.shape[0] == 0 for _, m in leaves)
+    want = oracle.ryser(A)
+    assert abs(weighted(oracle, leaves) - want) <= 1e-13 * abs(want)

@@ -16,6 +16,15 @@ from paper_2502_16577_amd import api
 from paper_2502_16577_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
+
+
+def scaled_perm(d, e, perm_pattern):
+    """perm(D P E) = prod d prod e perm(P), in exact rational arithmetic."""
+    from fractions import Fraction
+    s = Fraction(perm_pattern)
+    for v in list(d) + list(e):
+        s *= Fraction(float(v))
+    return float(s)
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "full_size.json")
 
 
@@ -88,3 +97,18 @@ def test_full_size_sparse40_pattern():
     want = float(g["value"])  # the exact integer, below 2^53
     got = api.perm_sparse_f64(40, cp, ri, v).item()
     assert abs(got - want) <= 1e-10 * want, (got, want)
+
+
+@pytest.mark.parametrize("fn", [api.perm_sparse_f64, api.perm_sparse_f64_staged])
+def test_full_size_sparse40_scaled_values(fn):
+    # the 40 x 40 pattern with entries d_i e_j (d, e uniform in [0.5, 1.5)):
+    # perm = prod d prod e perm(pattern); the rounding of d_i e_j moves the
+    # permanent by at most 40 u relative
+    g = json.load(open(GOLDEN))["sparse40"]
+    a = W.sparse_rows(40, 6, W.SEED_SPARSE40).astype(np.float64)
+    assert W.digest(W.sparse_rows(40, 6, W.SEED_SPARSE40)) == g["digest"]
+    d, e = W.scaling_vectors(40, 7040)
+    cp, ri, v = W.to_csc(a * np.outer(d, e))
+    want = scaled_perm(d, e, int(g["value"]))
+    got = fn(40, cp, ri, v).item()
+    assert abs(got - want) <= 1e-10 * want, (fn.__name__, got, want)
