@@ -34,6 +34,7 @@ same matrix's Gray walk, on the cores this process may use.
 from __future__ import annotations
 
 import argparse
+import fractions
 import json
 import os
 import sys
@@ -362,18 +363,25 @@ def measure_rows():
         rows[name] = rec
 
     # a8: sparse real, the 40x40 pattern with U[0,1) values (stored oracle
-    # value of Algorithm 2's CSC walk), else with its 0/1 values (exact)
+    # value of Algorithm 2's CSC walk), else with entries d_i e_j (d, e
+    # uniform in [0.5, 1.5), seed 7040): perm = prod d prod e times the
+    # pattern's exact permanent
     n = 40
     pat = workloads.sparse_rows(n, 6, workloads.SEED_SPARSE40)
+    assert workloads.digest(pat) == full["sparse40"]["digest"]
     if "sparse40u" in full:
         a = pat * workloads.uniform(n, workloads.SEED_SPARSE40_VALUES)
         g = full["sparse40u"]
+        assert workloads.digest(a) == g["digest"]
         values = "U[0,1) (seed 16585)"
     else:
-        a = pat.astype(np.float64)
-        g = {"digest": workloads.digest(pat), "value": [float(full["sparse40"]["value"]), 0.0]}
-        values = "1 (the 0/1 pattern as reals)"
-    assert workloads.digest(a if "sparse40u" in full else pat) == g["digest"]
+        d, e = workloads.scaling_vectors(n, 7040)
+        a = pat * np.outer(d, e)
+        exact = fractions.Fraction(int(full["sparse40"]["value"]))
+        for v in list(d) + list(e):
+            exact *= fractions.Fraction(float(v))
+        g = {"value": [float(exact), 0.0]}
+        values = "d_i e_j, d and e uniform in [0.5, 1.5) (seed 7040)"
     cp, ri, va = workloads.to_csc(a)
     out = torch.empty((), dtype=torch.float64, device=dev)
     wss = torch.empty(api.workspace_bytes(3, n, len(ri)), dtype=torch.uint8, device=dev)
@@ -435,6 +443,8 @@ def bench_rows():
         print(_json({"row": name, **rec}), flush=True)
     n = 40
     a = workloads.sparse_rows(n, 6, workloads.SEED_SPARSE40)
+    g = _golden("full_size.json")["sparse40"]
+    assert workloads.digest(a) == g["digest"]
     cp, ri, va = workloads.to_csc(a)
     api.perm_sparse_decomp(n, cp, ri, va)
     torch.cuda.synchronize()
@@ -442,8 +452,10 @@ def bench_rows():
     v = api.perm_sparse_decomp(n, cp, ri, va).item()
     dt = time.perf_counter() - t0
     print(_json({"row": "next-3 DecompRyser", "workload": "40x40 0/1, 6 per row (seed 16582): "
-                      "DM pruning + Forbert-Marx, leaves batched on the GPU (host decomposition "
-                      "included)", "seconds": dt, "perm": v}), flush=True)
+                      "DM pruning + Forbert-Marx (leaves of order <= 2 folded on the host), "
+                      "large leaves as real sweeps, the rest batched (host decomposition "
+                      "included)", "seconds": dt, "perm": v,
+                 "rel_err": abs(v - int(g["value"])) / int(g["value"])}), flush=True)
 
 
 # Best published GPU kernel (x_reg-A_shr-rebuild with CEG, Quadro GV100) of

@@ -325,19 +325,39 @@ static int sparse_args(int n, const int32_t *col_ptr, const int32_t *row_idx, co
     return check_ws(ws, ws_bytes, perm_workspace_bytes(PERM_KIND_SPARSE_F64, n, nnz));
 }
 
+// Columns of a CSC matrix by ascending nonzero count (stable): new column jn
+// is old column order[jn].  The permanent is invariant under column
+// permutations; in the Gray walk the low columns flip most often (column 0
+// every other step) and the last column never, so with the sparsest columns
+// lowest each step updates, and rounds, the fewest entries of x.  On the
+// 40 x 40 six-per-row pattern with scaled values this takes the dense sweep's
+// relative error from 3.5e-10 (given order) to 7e-11 (descending: 1e-8).
+static std::vector<int> columns_by_count(int n, const int32_t *col_ptr)
+{
+    std::vector<int> order(n);
+    for (int j = 0; j < n; ++j) order[j] = j;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        return col_ptr[x + 1] - col_ptr[x] < col_ptr[y + 1] - col_ptr[y];
+    });
+    return order;
+}
+
 // Staged-column sweep: the matrix is scattered into a row-major copy behind
-// the dense workspace and swept like a dense matrix (every step adds a whole
-// column, zeros included).  Used for n < kSparseGenMinN (at most 2^12 steps)
-// and by perm_sparse_f64_staged.
+// the dense workspace, its columns by ascending count, and swept like a
+// dense matrix (every step adds a whole column, zeros included).  Used for
+// n < kSparseGenMinN (at most 2^12 steps) and by perm_sparse_f64_staged.
 static int sparse_staged(int n, const int32_t *col_ptr, const int32_t *row_idx,
                          const double *vals, char *base, double *out, hipStream_t st)
 {
     const size_t off = perm_workspace_bytes(PERM_KIND_DENSE_F64, n, 0);
     double *dense = reinterpret_cast<double *>(base + off);
     const int32_t nnz = col_ptr[n];
+    const std::vector<int> order = columns_by_count(n, col_ptr);
     std::vector<int32_t> pos(nnz);
-    for (int j = 0; j < n; ++j)
-        for (int32_t q = col_ptr[j]; q < col_ptr[j + 1]; ++q) pos[q] = row_idx[q] * n + j;
+    for (int jn = 0; jn < n; ++jn) {
+        const int j = order[jn];
+        for (int32_t q = col_ptr[j]; q < col_ptr[j + 1]; ++q) pos[q] = row_idx[q] * n + jn;
+    }
     int rc = launch_stage_sparse(n, pos.data(), vals, nnz, dense, st);
     if (rc != PERM_OK) return rc;
     return launch_dense_f64(n, dense, n, out, base, st);
@@ -356,15 +376,10 @@ int perm_sparse_f64(int n, const int32_t *col_ptr, const int32_t *row_idx, const
     // Algorithm 2's update: a step adds only the flipped column's nonzeros.
     // With x in registers a run-time row index cannot name a register, so
     // the update lists are compiled into a kernel for this pattern.
-    // Columns by ascending count (the permanent is invariant under column
-    // permutations): the low columns, flipped at 15 of every 16 steps, then
-    // cost the fewest updates, and the densest column is the never-flipped
-    // last one.
-    std::vector<int> order(n);
-    for (int j = 0; j < n; ++j) order[j] = j;
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-        return col_ptr[x + 1] - col_ptr[x] < col_ptr[y + 1] - col_ptr[y];
-    });
+    // Columns by ascending count: the low columns, flipped at 15 of every
+    // 16 steps, then cost the fewest updates (and round the fewest entries
+    // of x), and the densest column is the never-flipped last one.
+    const std::vector<int> order = columns_by_count(n, col_ptr);
     // Rows (also free to permute): those with a nonzero in the four lowest
     // columns go last.  Steps inside a 16-step block change only these rows,
     // and the generated product evaluates rows in a fixed order, so the

@@ -66,11 +66,16 @@ def test_sparse_dense_patterns(oracle):
 
 
 def test_staged_matches_dense_bitwise():
+    # the staged path is the dense sweep of the matrix with its columns in
+    # ascending order of nonzero count (stable)
     n = 25
     a = W.sparse_rows(n, 6, 5).astype(np.float64) * W.uniform(n, 6)
+    a[:, 3] = 0.0
+    a[[2, 7, 11], 3] = 0.5       # uneven column counts
     cp, ri, v = W.to_csc(a)
     s = api.perm_sparse_f64_staged(n, cp, ri, v).item()
-    d = api.perm_dense_f64(torch.from_numpy(a).to("cuda:0")).item()
+    order = np.argsort(np.count_nonzero(a, axis=0), kind="stable")
+    d = api.perm_dense_f64(torch.from_numpy(np.ascontiguousarray(a[:, order])).to("cuda:0")).item()
     assert s == d
 
 
