@@ -153,12 +153,16 @@ __device__ __forceinline__ void grad_item(const double *__restrict__ acol,
             }
         }
     };
+    // One staged copy: the sign of the flip goes into the multiplier, which
+    // halves the scalar-cache footprint of an item's columns.
+    const double nact = -act;
     auto flip = [&](int j, bool add) {
-        const double *a = (add ? acol : aneg) + W * (j * NP + row0);
+        const double *a = acol + W * (j * NP + row0);
+        const double sa = add ? act : nact;
 #pragma unroll
         for (int t = 0; t < R; ++t) {
-            xr[t] = __builtin_fma(act, a[W * t], xr[t]);
-            if (CPLX) xi[t] = __builtin_fma(act, a[W * t + 1], xi[t]);
+            xr[t] = __builtin_fma(sa, a[W * t], xr[t]);
+            if (CPLX) xi[t] = __builtin_fma(sa, a[W * t + 1], xi[t]);
         }
     };
 
@@ -168,6 +172,35 @@ __device__ __forceinline__ void grad_item(const double *__restrict__ acol,
         if (j == N - 1) return 1.0;
         const uint64_t g = ((w * kWave + lk) << c) | l;
         return (((g ^ (g >> 1)) >> j) & 1u) ? 1.0 : -1.0;
+    };
+
+    // The low columns' share of the step before (its V is in vbuf, written by
+    // this wave before these reads in program order; a wave's LDS accesses
+    // complete in order): lane (jj, kq) adds 16 lanes' V of slice row jj
+    // (lanes 16 kq .. 16 kq + 15), and the MFMA adds the four kq partial
+    // sums and multiplies by tau_j(l) for the columns j < f.  The reads of a
+    // component are issued by lo_read and consumed by lo_add, with other
+    // work of the current step in between to hide the LDS latency.
+    double lv[16];
+    double lsum[W];
+    const int jr = jj < R ? jj : 0;      // lanes jj >= R read row 0 and drop it
+    auto lo_read = [&](int q) {
+        const double *col = vbuf + q * kWave * STRIDE + jr + 16 * kq * STRIDE;
+#pragma unroll
+        for (int m = 0; m < 16; ++m) lv[m] = col[m * STRIDE];
+    };
+    auto lo_add = [&](int q) {
+#pragma unroll
+        for (int span = 8; span >= 1; span /= 2)
+#pragma unroll
+            for (int m = 0; m < span; ++m) lv[m] += lv[m + span];
+        lsum[q] = (jj < R) ? lv[0] : 0.0;
+    };
+    auto lo_apply = [&](uint32_t l) {
+        const double bl = (jj < f) ? tau(0, l, jj) : 0.0;
+#pragma unroll
+        for (int q = 0; q < W; ++q)
+            acc_lo[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(lsum[q], bl, acc_lo[q], 0, 0, 0);
     };
 
     // One step of the walk: the leave-one-out products of this slice's rows,
@@ -184,6 +217,9 @@ __device__ __forceinline__ void grad_item(const double *__restrict__ acol,
     // 3 (R - 1) complex products per lane and step in all.
     auto step = [&](uint32_t l, auto neg_tag) {
         constexpr bool NEG = decltype(neg_tag)::value;
+        // the previous step's low-column values (written by this wave, in
+        // order before these reads), unless this step opens a window
+        const bool pend = want_grad && f > 0 && (l & fmask) != 0u;
         // block b holds rows [b R / NB, (b + 1) R / NB): every block non-empty
         constexpr int NB = R >= 8 ? 4 : (R >= 4 ? 2 : 1);
         auto beg = [](int b) { return b * R / NB; };
@@ -212,6 +248,12 @@ __device__ __forceinline__ void grad_item(const double *__restrict__ acol,
             Qr[b] = fr;
             Qi[b] = fi;
             gmul<CPLX>(fr, fi, Pr[b], Pi[b]);
+        }
+        // keeps the adds of the low-column reads after the product above
+        __builtin_amdgcn_sched_barrier(0);
+        if (pend) {
+            lo_add(0);
+            if (CPLX) lo_read(1);
         }
         // the other slices' products, through LDS (the buffer alternates
         // with the step parity, so one barrier per step suffices)
@@ -247,6 +289,10 @@ __device__ __forceinline__ void grad_item(const double *__restrict__ acol,
             if (h == (NEG ? 1 : 0)) acc_add(sr, er, fr * orr);
         }
         if (!want_grad) return;
+        if (pend) {
+            if (CPLX) lo_add(1);
+            lo_apply(l - 1);
+        }
         // E_b = (-1)^g O prod_{b' != b} P_b', formed from the last block down
         double Er[NB], Ei[NB];
         {
@@ -261,7 +307,8 @@ __device__ __forceinline__ void grad_item(const double *__restrict__ acol,
             Er[0] = tr;
             Ei[0] = ti;
         }
-        // within each block from its last row: L_i = pre_i E_b (later rows)
+        // within each block from its last row: L_i = pre_i E_b (later rows);
+        // V goes to this wave's transposition buffer for the low columns
         double *vr = vbuf + lane * STRIDE;
         double *vi = vbuf + (W - 1) * kWave * STRIDE + lane * STRIDE;
 #pragma unroll
@@ -281,39 +328,17 @@ __device__ __forceinline__ void grad_item(const double *__restrict__ acol,
                     if (CPLX) vi[i] = li;
                 }
             }
-        if (f == 0) return;
-        wave_sync_lds();
-        // low columns j < f: lane sums 16 lanes' V (lanes kq*16 .. +15) of
-        // slice row jj; the MFMA adds the 4 partial sums and multiplies by
-        // tau_j(l) (the same for every lane).
-        const double bl = (jj < f) ? tau(0, l, jj) : 0.0;
-#pragma unroll
-        for (int q = 0; q < W; ++q) {
-            double s = 0.0;
-            if (jj < R) {
-                // reads are issued eight at a time before their adds, so the
-                // LDS latency is paid twice per component rather than per read
-                const double *col = vbuf + q * kWave * STRIDE + jj + 16 * kq * STRIDE;
-#pragma unroll
-                for (int half = 0; half < 2; ++half) {
-                    double v[8];
-#pragma unroll
-                    for (int rr = 0; rr < 8; ++rr) v[rr] = col[(8 * half + rr) * STRIDE];
-#pragma unroll
-                    for (int span = 4; span >= 1; span /= 2)
-#pragma unroll
-                        for (int rr = 0; rr < span; ++rr) v[rr] += v[rr + span];
-                    s = half ? s + v[0] : v[0];
-                }
-            }
-            acc_lo[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(s, bl, acc_lo[q], 0, 0, 0);
-        }
-        wave_sync_lds();
     };
 
-    // End of a window: contract the lanes' window sums with their tau for
-    // the columns j >= f, then fold everything into the double-double G.
     auto close_window = [&](uint32_t l0) {
+        if (f > 0) {  // the window's last step
+#pragma unroll
+            for (int q = 0; q < W; ++q) {
+                lo_read(q);
+                lo_add(q);
+            }
+            lo_apply(l0 + fmask);
+        }
         v4d acc_hi[W][MT];  // the window's contraction (slice rows x all columns)
 #pragma unroll
         for (int q = 0; q < W; ++q)
@@ -375,6 +400,8 @@ __device__ __forceinline__ void grad_item(const double *__restrict__ acol,
     };
 
     for (uint32_t l = 0; l < C; l += 2) {
+        // the previous step's low-column reads go out before the flip
+        if (want_grad && f > 0 && (l & fmask) != 0u) lo_read(0);
         if ((l & rmask) == 0) {
             reseed(l);
         } else {
@@ -383,6 +410,7 @@ __device__ __forceinline__ void grad_item(const double *__restrict__ acol,
         }
         step(l, std::false_type{});
         if (want_grad && f == 0) close_window(l);
+        if (want_grad && f > 0) lo_read(0);
         if (c == 1) {
             reseed(l + 1);  // the column-0 sign depends on the lane when c == 1
         } else {

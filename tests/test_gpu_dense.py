@@ -182,6 +182,26 @@ def test_all_equal_paper_size(n):
         assert abs(got - exact) <= 1e-10 * exact, (n, got, exact, abs(got - exact) / exact)
 
 
+def test_all_equal_n40_within_forward_error():
+    # Table 3's n = 40 shape (2^39 steps).  Here relative 1e-10 is below what
+    # FP64 products of FP64-rounded x can reach: rounding x alone moves the
+    # sum by 8.8e-10 of the permanent (the all-equal rounding model), so the
+    # gate is the forward-error scale n u R(A), with R(A) in closed form
+    # (2 sum_k C(n-1, k) |k + 1 - n/2|^n a^n), in every accumulation mode.
+    n = 40
+    a = np.full((n, n), 0.91)
+    aq = fractions.Fraction(0.91)
+    exact = math.factorial(n) * aq ** n
+    r = 2 * sum(math.comb(n - 1, k) * abs(fractions.Fraction(2 * (k + 1) - n, 2)) ** n
+                for k in range(n)) * aq ** n
+    gate = float(n * fractions.Fraction(1, 2 ** 53) * r)
+    A = torch.from_numpy(a).to(DEV)
+    for acc in (api.ACC_TWOSUM, api.ACC_KAHAN, api.ACC_PLAIN):
+        got = api.perm_dense_f64_ex(A, accumulation=acc).item()
+        err = abs(fractions.Fraction(got) - exact)
+        assert err <= gate, (acc, got, float(exact), float(err / exact))
+
+
 def test_empty_and_degenerate_inputs():
     # n = 0: the empty product
     z = torch.zeros((0, 0), dtype=torch.complex128, device=DEV)
