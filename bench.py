@@ -52,7 +52,7 @@ GOLDEN = os.path.join(ROOT, "tests", "golden")
 # plain 1 GiB copy (profiles/sweep_dense_f64_n32_u01.md).  Valid only for the
 # kernel source they were measured on; reported as null once it changes.
 COUNTERS_SRC = os.path.join(ROOT, "paper_2502_16577_amd", "csrc", "sweep_f64.hip")
-COUNTERS_SRC_SHA256 = "2e9356c7e13965c121678f44cb3f3c16b6568bb55b9148af0310e214dab47f79"
+COUNTERS_SRC_SHA256 = "83a40bf7c5684fc647b774e18a7133a1130a54295c413c4d81f1d66160b75a05"
 TRAFFIC_BYTES_PER_LAUNCH = 188 * 1024 * 2.000 + 32 * 1024 * 1.000
 
 

@@ -23,18 +23,22 @@
 //     product, G (rows x n) += W (rows x 64) T (64 x n), K running over lanes.
 //   * columns j < f: tau_j depends only on the step (the same for every lane
 //     of the wave), so per step G[:, j] += tau_j U with U = sum over lanes of
-//     V; each lane sums 16 lanes' V from LDS and one MFMA with the B operand
-//     tau_j repeated down K adds the four partial sums and forms the outer
-//     product with tau in one instruction.
+//     V; each lane sums 16 lanes' V from LDS (the reads of one step overlap
+//     the next step's flip and product).  For j >= 1, tau_j is the same at
+//     both steps of an aligned pair, so one MFMA per pair, with the B operand
+//     tau_j repeated down K, adds the four partial sums of the pair and forms
+//     the outer product with tau; column 0 is summed per lane with its sign
+//     and contracted at the end of the window.
 // MFMA operand layout (gfx950): A[i][k] at lane i + 16k, B[k][j] at lane
 // j + 16k, D[i][j] at lane j + 16 (i mod 4), register i / 4.
 // Accumulators fold into the item's double-double partial G in global memory
 // at the end of every window (2^9 steps at most, so plain FP64 accumulation
 // never spans more than 512 steps of 64 subsets).
 //
-// Staged layout: acol / aneg hold column j at [W (j NP + i)] with NP = NS R
-// rows (rows >= n are zero) and x0 has NP entries (1 for rows >= n), so a
-// padding row keeps x = 1 and changes no product.
+// Staged layout: acol holds column j at [W (j NP + i)] with NP = NS R rows
+// (rows >= n are zero) and x0 has NP entries (1 for rows >= n), so a padding
+// row keeps x = 1 and changes no product.  A flip's sign goes into the FMA
+// multiplier, so no negated copy is staged.
 #pragma once
 
 #include <type_traits>
@@ -82,7 +86,7 @@ struct GradItemShape {
 
 // Called by all NS waves of a block (each must make the call: it
 // synchronises the block once per step).
-// Inputs: staged acol / aneg / x0 (layout above); the item's index w (its
+// Inputs: staged acol / x0 (layout above); the item's index w (its
 // subsets are 64 w .. 64 w + 63); log2 chunk c >= 1; log2 re-seed interval
 // r <= c - 1; lanes_active (subsets K >= lanes_active idle with x = 0).
 // Outputs: perm_out[0..1] (double-double re, im of the item's share of
@@ -91,7 +95,6 @@ struct GradItemShape {
 // sum_g (-1)^g L_i tau_j; each wave zeroes and fills its own rows).
 template <int N, bool CPLX>
 __device__ __forceinline__ void grad_item(const double *__restrict__ acol,
-                                          const double *__restrict__ aneg,
                                           const double *__restrict__ x0, uint64_t w, int c, int r,
                                           uint64_t lanes_active, dd *__restrict__ perm_out,
                                           dd *__restrict__ g_out, bool want_grad,
@@ -153,8 +156,8 @@ __device__ __forceinline__ void grad_item(const double *__restrict__ acol,
             }
         }
     };
-    // One staged copy: the sign of the flip goes into the multiplier, which
-    // halves the scalar-cache footprint of an item's columns.
+    // The sign of the flip goes into the multiplier (one staged copy, half
+    // the scalar-cache footprint of two).
     const double nact = -act;
     auto flip = [&](int j, bool add) {
         const double *a = acol + W * (j * NP + row0);
@@ -196,11 +199,43 @@ __device__ __forceinline__ void grad_item(const double *__restrict__ acol,
             for (int m = 0; m < span; ++m) lv[m] += lv[m + span];
         lsum[q] = (jj < R) ? lv[0] : 0.0;
     };
-    auto lo_apply = [&](uint32_t l) {
-        const double bl = (jj < f) ? tau(0, l, jj) : 0.0;
+    // The MFMA runs once per aligned pair of steps (l even, l + 1): tau_j for
+    // j >= 1 is the same at both (only bit 0 of the step changes), so the
+    // pair's partial sums gs are multiplied once; column 0, whose tau flips
+    // inside the pair, is accumulated per lane (y0) and contracted at the end
+    // of the window.  Called only with f >= 1 (windows of whole pairs).
+    double gs[W], y0[W];
 #pragma unroll
-        for (int q = 0; q < W; ++q)
-            acc_lo[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(lsum[q], bl, acc_lo[q], 0, 0, 0);
+    for (int q = 0; q < W; ++q) {
+        gs[q] = 0.0;
+        y0[q] = 0.0;
+    }
+    auto lo_apply = [&](uint32_t l) {
+        // tau_0 of step l: bit 0 of its Gray code (bits 0 and 1 are local)
+        const double t0 = ((l ^ (l >> 1)) & 1u) ? 1.0 : -1.0;
+#pragma unroll
+        for (int q = 0; q < W; ++q) {
+            gs[q] += lsum[q];
+            y0[q] = __builtin_fma(t0, lsum[q], y0[q]);
+        }
+        if ((l & 1u) == 1u) {
+            const double bl = (jj >= 1 && jj < f) ? tau(0, l, jj) : 0.0;
+#pragma unroll
+            for (int q = 0; q < W; ++q) {
+                acc_lo[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(gs[q], bl, acc_lo[q], 0, 0, 0);
+                gs[q] = 0.0;
+            }
+        }
+    };
+    // end of a window: column 0 from the per-lane sums (B = e_0 adds the
+    // four kq partial sums of each row into column 0)
+    auto lo_fold0 = [&]() {
+        const double b0 = (jj == 0) ? 1.0 : 0.0;
+#pragma unroll
+        for (int q = 0; q < W; ++q) {
+            acc_lo[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(y0[q], b0, acc_lo[q], 0, 0, 0);
+            y0[q] = 0.0;
+        }
     };
 
     // One step of the walk: the leave-one-out products of this slice's rows,
@@ -338,6 +373,7 @@ __device__ __forceinline__ void grad_item(const double *__restrict__ acol,
                 lo_add(q);
             }
             lo_apply(l0 + fmask);
+            lo_fold0();
         }
         v4d acc_hi[W][MT];  // the window's contraction (slice rows x all columns)
 #pragma unroll

@@ -105,8 +105,6 @@ GradWs grad_ws_layout(int n, int components, int64_t waves)
     const size_t nn = size_t(n) * np * size_t(components) * sizeof(double);
     L.acol = off;
     off += align256(nn);
-    L.aneg = off;
-    off += align256(nn);
     L.x0 = off;
     off += align256(np * size_t(components) * sizeof(double));
     L.perm_partials = off;

@@ -116,7 +116,7 @@ void derive(perm_plan &P)
             M.waves = int32_t(std::max<int64_t>(1, lanes / kWave));
         }
         M.stage = stage;
-        stage += 4 * int64_t(k) * batch_rows(k) + 2 * int64_t(batch_rows(k));
+        stage += 2 * int64_t(k) * batch_rows(k) + 2 * int64_t(batch_rows(k));
         M.item0 = item0;
         item0 += M.waves;
         M.gbase = gdd;

@@ -163,7 +163,7 @@ struct GradPlan {
 GradPlan plan_grad(int n);
 
 struct GradWs {
-    size_t acol = 0, aneg = 0, x0 = 0;  // as DenseWs
+    size_t acol = 0, x0 = 0;            // staged columns (grad_rows(n) rows each), start vector
     size_t perm_partials = 0;           // waves * 2 dd
     size_t grad_partials = 0;           // waves * components * n * n dd
     size_t total = 0;

@@ -21,7 +21,7 @@
 namespace perm {
 
 // Stages every matrix in grad_item's layout: acol[2(j kp + i) + {re,im}]
-// with kp = batch_rows(k) rows per column (rows >= k zero), aneg = -acol,
+// with kp = batch_rows(k) rows per column (rows >= k zero), then
 // x0[2 i + {re,im}] for i < kp (1 for rows >= k), at stage + mats[m].stage
 // (doubles).  One block per matrix.
 __global__ __launch_bounds__(kBlock) void batched_prep(const BatchMatDev *__restrict__ mats,
@@ -33,15 +33,12 @@ __global__ __launch_bounds__(kBlock) void batched_prep(const BatchMatDev *__rest
     const int kp = batch_rows(k);
     const perm_c128 *A = data + M.data_off;
     double *acol = stage + M.stage;
-    double *aneg = acol + 2 * k * kp;
-    double *x0 = aneg + 2 * k * kp;
+    double *x0 = acol + 2 * k * kp;
     for (int idx = threadIdx.x; idx < k * kp; idx += blockDim.x) {
         const int j = idx / kp, i = idx - j * kp;
         const perm_c128 v = i < k ? A[i * k + j] : perm_c128{0.0, 0.0};
         acol[2 * idx] = v.re;
         acol[2 * idx + 1] = v.im;
-        aneg[2 * idx] = -v.re;
-        aneg[2 * idx + 1] = -v.im;
     }
     for (int i = k + int(threadIdx.x); i < kp; i += blockDim.x) {
         x0[2 * i] = 1.0;
@@ -81,10 +78,9 @@ __device__ __forceinline__ void batched_item(const BatchMatDev &M, int w,
         }
     } else {
         constexpr int KP = GradItemShape<K, true>::NP;
-        const double *aneg = acol + 2 * K * KP;
-        const double *x0 = aneg + 2 * K * KP;
+        const double *x0 = acol + 2 * K * KP;
         const uint64_t lanes_active = (uint64_t(1) << (K - 1)) >> M.c;
-        grad_item<K, true>(acol, aneg, x0, uint64_t(w), M.c, M.r, lanes_active, perm_out, g_out,
+        grad_item<K, true>(acol, x0, uint64_t(w), M.c, M.r, lanes_active, perm_out, g_out,
                            want_grad, lds);
     }
 }

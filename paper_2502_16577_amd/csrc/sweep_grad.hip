@@ -17,13 +17,12 @@ namespace perm {
 
 constexpr int kGradBlock = kGradSlices * kWave;  // one grad_item per block
 
-// Staging for grad_item: column-major +-A with np rows per column (rows >= n
+// Staging for grad_item: column-major A with np rows per column (rows >= n
 // zero) and x0 with np entries (1 for rows >= n).  A is row-major with W
 // doubles per entry and a row stride of lda entries.
 template <bool CPLX>
 __global__ __launch_bounds__(kBlock) void prep_grad(int n, int np, const double *__restrict__ A,
                                                     int64_t lda, double *__restrict__ acol,
-                                                    double *__restrict__ aneg,
                                                     double *__restrict__ x0)
 {
     constexpr int W = CPLX ? 2 : 1;
@@ -33,7 +32,6 @@ __global__ __launch_bounds__(kBlock) void prep_grad(int n, int np, const double 
         for (int q = 0; q < W; ++q) {
             const double v = i < n ? A[(int64_t(i) * lda + j) * W + q] : 0.0;
             acol[W * idx + q] = v;
-            aneg[W * idx + q] = -v;
         }
     }
     for (int i = threadIdx.x; i < np; i += blockDim.x) {
@@ -55,7 +53,6 @@ __global__ __launch_bounds__(kBlock) void prep_grad(int n, int np, const double 
 // receive the item's shares.
 template <int N, bool CPLX>
 __device__ __forceinline__ void sweep_grad_body(const double *__restrict__ acol,
-                                                const double *__restrict__ aneg,
                                                 const double *__restrict__ x0,
                                                 dd *__restrict__ perm_part, dd *__restrict__ g_part,
                                                 int c, int r, int64_t lanes_active, int want_grad)
@@ -64,7 +61,7 @@ __device__ __forceinline__ void sweep_grad_body(const double *__restrict__ acol,
     static_assert(S::THREADS == kGradBlock, "block shape");
     __shared__ double lds[S::LDS_DOUBLES];
     const uint64_t w = blockIdx.x;
-    grad_item<N, CPLX>(acol, aneg, x0, w, c, r, uint64_t(lanes_active), perm_part + 2 * w,
+    grad_item<N, CPLX>(acol, x0, w, c, r, uint64_t(lanes_active), perm_part + 2 * w,
                        g_part + w * uint64_t(S::W * N * N), want_grad != 0, lds);
 }
 
@@ -72,21 +69,19 @@ __device__ __forceinline__ void sweep_grad_body(const double *__restrict__ acol,
 // as in the batched kernel of orders 17..24); the compiler is held to that.
 template <int N, bool CPLX>
 __global__ __launch_bounds__(kGradBlock) __attribute__((amdgpu_waves_per_eu(2))) void
-sweep_grad(const double *__restrict__ acol, const double *__restrict__ aneg,
-           const double *__restrict__ x0, dd *__restrict__ perm_part, dd *__restrict__ g_part, int c,
+sweep_grad(const double *__restrict__ acol, const double *__restrict__ x0, dd *__restrict__ perm_part, dd *__restrict__ g_part, int c,
            int r, int64_t lanes_active, int want_grad)
 {
-    sweep_grad_body<N, CPLX>(acol, aneg, x0, perm_part, g_part, c, r, lanes_active, want_grad);
+    sweep_grad_body<N, CPLX>(acol, x0, perm_part, g_part, c, r, lanes_active, want_grad);
 }
 
 // Orders 25..32: one wave per SIMD.
 template <int N, bool CPLX>
 __global__ __launch_bounds__(kGradBlock) void sweep_grad_large(
-    const double *__restrict__ acol, const double *__restrict__ aneg, const double *__restrict__ x0,
-    dd *__restrict__ perm_part, dd *__restrict__ g_part, int c, int r, int64_t lanes_active,
+    const double *__restrict__ acol, const double *__restrict__ x0, dd *__restrict__ perm_part, dd *__restrict__ g_part, int c, int r, int64_t lanes_active,
     int want_grad)
 {
-    sweep_grad_body<N, CPLX>(acol, aneg, x0, perm_part, g_part, c, r, lanes_active, want_grad);
+    sweep_grad_body<N, CPLX>(acol, x0, perm_part, g_part, c, r, lanes_active, want_grad);
 }
 
 // n = 1: perm = a, dperm/da = 1.
@@ -148,17 +143,16 @@ __global__ __launch_bounds__(kBlock) void finalize_perm_only(const dd *__restric
 }
 
 template <int N, bool CPLX>
-static void launch_grad_n(const GradPlan &p, const double *acol, const double *aneg,
-                          const double *x0, dd *pp, dd *gp, bool want_grad, double *out_perm,
+static void launch_grad_n(const GradPlan &p, const double *acol, const double *x0, dd *pp, dd *gp, bool want_grad, double *out_perm,
                           double *out_grad, hipStream_t stream)
 {
     if constexpr (N <= 24)
         hipLaunchKernelGGL((sweep_grad<N, CPLX>), dim3(unsigned(p.waves)), dim3(kGradBlock), 0,
-                           stream, acol, aneg, x0, pp, gp, p.log2_chunk, p.log2_reseed,
+                           stream, acol, x0, pp, gp, p.log2_chunk, p.log2_reseed,
                            p.lanes_active, int(want_grad));
     else
         hipLaunchKernelGGL((sweep_grad_large<N, CPLX>), dim3(unsigned(p.waves)), dim3(kGradBlock),
-                           0, stream, acol, aneg, x0, pp, gp, p.log2_chunk, p.log2_reseed,
+                           0, stream, acol, x0, pp, gp, p.log2_chunk, p.log2_reseed,
                            p.lanes_active, int(want_grad));
     if (want_grad)
         hipLaunchKernelGGL((finalize_grad<N, CPLX>), dim3(unsigned(N * N * (CPLX ? 2 : 1))),
@@ -168,8 +162,8 @@ static void launch_grad_n(const GradPlan &p, const double *acol, const double *a
                            (N & 1) ? 2.0 : -2.0, out_perm);
 }
 
-using GradLauncher = void (*)(const GradPlan &, const double *, const double *, const double *,
-                              dd *, dd *, bool, double *, double *, hipStream_t);
+using GradLauncher = void (*)(const GradPlan &, const double *, const double *, dd *, dd *, bool,
+                              double *, double *, hipStream_t);
 
 template <bool CPLX, int... Ns>
 struct GradTable {
@@ -208,16 +202,16 @@ GradPlan plan_grad(int n)
     return p;
 }
 
-static int launch_stage(int n, bool cplx, const void *A, int64_t lda, double *acol, double *aneg,
-                        double *x0, hipStream_t stream)
+static int launch_stage(int n, bool cplx, const void *A, int64_t lda, double *acol, double *x0,
+                        hipStream_t stream)
 {
     const int np = grad_rows(n);
     if (cplx)
         hipLaunchKernelGGL(prep_grad<true>, dim3(1), dim3(kBlock), 0, stream, n, np,
-                           static_cast<const double *>(A), lda, acol, aneg, x0);
+                           static_cast<const double *>(A), lda, acol, x0);
     else
         hipLaunchKernelGGL(prep_grad<false>, dim3(1), dim3(kBlock), 0, stream, n, np,
-                           static_cast<const double *>(A), lda, acol, aneg, x0);
+                           static_cast<const double *>(A), lda, acol, x0);
     return PERM_OK;
 }
 
@@ -240,14 +234,13 @@ int launch_grad_or_small(int n, bool cplx, const void *A, int64_t lda, void *out
         return hipGetLastError() == hipSuccess ? PERM_OK : PERM_EHIP;
     }
     double *acol = reinterpret_cast<double *>(ws + L.acol);
-    double *aneg = reinterpret_cast<double *>(ws + L.aneg);
     double *x0 = reinterpret_cast<double *>(ws + L.x0);
     dd *pp = reinterpret_cast<dd *>(ws + L.perm_partials);
     dd *gp = reinterpret_cast<dd *>(ws + L.grad_partials);
-    launch_stage(n, cplx, A, lda, acol, aneg, x0, stream);
+    launch_stage(n, cplx, A, lda, acol, x0, stream);
     GradLauncher f = cplx ? GradC128Table::get(n) : GradF64Table::get(n);
     if (!f) return PERM_EUNSUPPORTED;
-    f(p, acol, aneg, x0, pp, gp, want_grad, static_cast<double *>(out_perm),
+    f(p, acol, x0, pp, gp, want_grad, static_cast<double *>(out_perm),
       static_cast<double *>(out_grad), stream);
     return hipGetLastError() == hipSuccess ? PERM_OK : PERM_EHIP;
 }
