@@ -451,10 +451,15 @@ def bench_rows():
     t0 = time.perf_counter()
     v = api.perm_sparse_decomp(n, cp, ri, va).item()
     dt = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ks = api._decompose_arrays(n, cp, ri, va, api.DECOMP_DM | api.DECOMP_FM | api.DECOMP_FOLD, 0)[0]
+    host = time.perf_counter() - t0
     print(_json({"row": "next-3 DecompRyser", "workload": "40x40 0/1, 6 per row (seed 16582): "
                       "DM pruning + Forbert-Marx (leaves of order <= 2 folded on the host), "
                       "large leaves as real sweeps, the rest batched (host decomposition "
-                      "included)", "seconds": dt, "perm": v,
+                      "included)", "seconds": dt, "host_decomposition_seconds": host,
+                 "leaves": int(len(ks)), "leaf_subset_steps": int(sum(2 ** (int(k) - 1) for k in ks)),
+                 "plain_sweep_subset_steps": 2 ** (n - 1), "perm": v,
                  "rel_err": abs(v - int(g["value"])) / int(g["value"])}), flush=True)
 
 

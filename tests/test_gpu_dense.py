@@ -150,11 +150,20 @@ def test_options_plain_and_split(oracle):
             assert abs(v - want) <= 1e-10 * abs(want), (acc, r, v, want)
 
 
-@pytest.mark.parametrize("name", ["u35"])
+def _have_golden(name):
+    with open(GOLDEN) as f:
+        return name in json.load(f)
+
+
+@pytest.mark.parametrize("name", ["u35", "u40"])
 def test_table4_shapes_against_oracle(name):
     # Table 4 shapes (Section 6.1): a dense U[0,1) matrix of order n (seed
     # 1000 + n), 2^(n-1) subset-steps, against the stored oracle value; the
-    # default sweep and the two other lane accumulation modes
+    # default sweep and the two other lane accumulation modes.  The n = 40
+    # value (2^39 steps) is computed by tests/golden/make_golden.py in
+    # resumable pieces; until it is stored the case is skipped.
+    if not _have_golden(name):
+        pytest.skip(f"{name}: oracle value not stored yet (tests/golden/make_golden.py {name})")
     g = _golden(name)
     n = g["n"]
     a = W.uniform(n, 1000 + n)
