@@ -355,26 +355,24 @@ int perm_batched_autotune(perm_plan *plan, const perm_c128 *data, perm_c128 *out
         }
     }
     hipStream_t st = static_cast<hipStream_t>(stream);
-    char *base = static_cast<char *>(ws);
     int rc = ensure_streams(P);
     if (rc != PERM_OK) return rc;
     drop_graph(P);  // waits for the last graph launch before the workspace is reused
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return PERM_EHIP;
-    // Times one candidate as the graph runs it: the groups' persistent
-    // kernels on their forked streams, concurrently (one untimed launch,
-    // then the average of two).
+    // Times one candidate exactly as it will run: captured into the plan's
+    // graph by perm_batched (one untimed launch, which also uploads the
+    // plan), then the average of two graph launches.
     auto time_it = [&](const BatchTuning &t, float &ms) -> int {
+        drop_graph(P);  // waits for the previous candidate's last launch
         P.tune = t;
         derive(P);
         P.uploaded_ws = nullptr;
-        int r = upload(P, base, st);
+        int r = perm_batched(plan, data, out, grad, 1, ws, ws_bytes, stream);
         if (r != PERM_OK) return r;
-        const BatchLaunch L = make_launch(P, base, data, out, grad);
-        if ((r = launch_batched_forked(L, st, P.side, P.fork, P.join)) != PERM_OK) return r;
         if (hipEventRecord(e0, st) != hipSuccess) return PERM_EHIP;
         for (int rep = 0; rep < 2; ++rep)
-            if ((r = launch_batched_forked(L, st, P.side, P.fork, P.join)) != PERM_OK) return r;
+            if ((r = perm_batched(plan, data, out, grad, 1, ws, ws_bytes, stream)) != PERM_OK) return r;
         if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
             return PERM_EHIP;
         hipEventElapsedTime(&ms, e0, e1);
@@ -413,6 +411,7 @@ int perm_batched_autotune(perm_plan *plan, const perm_c128 *data, perm_c128 *out
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
+    drop_graph(P);  // the graph holds the last candidate; the next call captures the best
     P.tune = best;
     derive(P);
     P.uploaded_ws = nullptr;
