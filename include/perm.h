@@ -267,8 +267,9 @@ int perm_grad(int n, int dtype, const void *A, int64_t lda, void *out_perm,
               void *out_grad, void *ws, size_t ws_bytes, void *stream);
 
 /*
- * Batched permanents (and gradients) of many small complex matrices of uneven
- * order, e.g. the amplitudes of photon-counting distributions (Section 1):
+ * Batched permanents (and gradients) of many small complex or real matrices
+ * of uneven order, e.g. the amplitudes of photon-counting distributions
+ * (Section 1) or the leaves of a Section 4 decomposition:
  * one persistent launch in which waves pull (matrix, chunk) work items,
  * largest orders first, and per-item partials are summed per matrix in a
  * fixed order.
@@ -286,6 +287,12 @@ typedef struct perm_plan perm_plan;
 
 int perm_batched_plan_create(int count, const int32_t *k, const int64_t *offset,
                              int want_grad, perm_plan **plan);
+/* The same for real matrices: offsets count doubles, data / out / grad are
+ * double, and the plan runs through the *_f64 entry points below (the
+ * complex ones return PERM_EINVAL for it, and the _f64 ones for a complex
+ * plan).  Each item is the real form of the same sweep (one component). */
+int perm_batched_plan_create_f64(int count, const int32_t *k, const int64_t *offset,
+                                 int want_grad, perm_plan **plan);
 void perm_plan_destroy(perm_plan *plan);
 
 /* Device workspace bytes for any launch (and any autotuning) of this plan. */
@@ -301,6 +308,10 @@ size_t perm_batched_workspace_bytes(const perm_plan *plan);
  */
 int perm_batched(perm_plan *plan, const perm_c128 *data, perm_c128 *out, perm_c128 *grad,
                  int use_graph, void *ws, size_t ws_bytes, void *stream);
+/* perm_batched for a plan made by perm_batched_plan_create_f64: data and
+ * grad row-major k x k doubles at the plan's offsets, out double[count]. */
+int perm_batched_f64(perm_plan *plan, const double *data, double *out, double *grad,
+                     int use_graph, void *ws, size_t ws_bytes, void *stream);
 
 /*
  * Autotuner: times the batch on this device as the graph runs it (each
@@ -319,6 +330,10 @@ int perm_batched(perm_plan *plan, const perm_c128 *data, perm_c128 *out, perm_c1
 int perm_batched_autotune(perm_plan *plan, const perm_c128 *data, perm_c128 *out,
                           perm_c128 *grad, void *ws, size_t ws_bytes, void *stream,
                           double *best_ms);
+/* perm_batched_autotune for a real plan (the kept tunings of real and
+ * complex plans are separate). */
+int perm_batched_autotune_f64(perm_plan *plan, const double *data, double *out, double *grad,
+                              void *ws, size_t ws_bytes, void *stream, double *best_ms);
 
 /* Plan introspection (any output may be NULL): number of work items, log2
  * steps per lane, grid[3] = persistent blocks of the groups of orders 1..16,
@@ -332,6 +347,9 @@ int perm_batched_plan_info(const perm_plan *plan, int64_t *n_items, int *log2_ch
  * decomposition).  Asynchronous on `stream`. */
 int perm_weighted_sum(int count, const double *weights, const perm_c128 *perms, perm_c128 *out,
                       void *stream);
+/* The same over real values (double perms[count], double out[1]). */
+int perm_weighted_sum_f64(int count, const double *weights, const double *perms, double *out,
+                          void *stream);
 
 /*
  * Sparse preprocessing of Section 4 (host only, no GPU work).

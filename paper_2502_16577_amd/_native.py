@@ -58,6 +58,10 @@ SIGNATURES = [
     ("perm_batched", _int, [_vp, _vp, _vp, _vp, _int, _vp, _sz, _vp]),
     ("perm_batched_autotune", _int, [_vp, _vp, _vp, _vp, _vp, _sz, _vp, ctypes.POINTER(ctypes.c_double)]),
     ("perm_weighted_sum", _int, [_int, _vp, _vp, _vp, _vp]),
+    ("perm_batched_plan_create_f64", _int, [_int, _vp, _vp, _int, ctypes.POINTER(_vp)]),
+    ("perm_batched_f64", _int, [_vp, _vp, _vp, _vp, _int, _vp, _sz, _vp]),
+    ("perm_batched_autotune_f64", _int, [_vp, _vp, _vp, _vp, _vp, _sz, _vp, ctypes.POINTER(ctypes.c_double)]),
+    ("perm_weighted_sum_f64", _int, [_int, _vp, _vp, _vp, _vp]),
     ("perm_decompose", _int, [_int, _vp, _vp, _vp, _i32, _int, _int, ctypes.POINTER(_vp)]),
     ("perm_decomp_info", _int, [_vp, ctypes.POINTER(_int), ctypes.POINTER(_int), ctypes.POINTER(_i64),
                                 ctypes.POINTER(_i64)]),

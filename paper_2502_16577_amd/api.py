@@ -266,21 +266,28 @@ def permanent(A: torch.Tensor) -> torch.Tensor:
 
 
 class BatchedPlan:
-    """Plan of a batched permanent (+ gradient) launch over packed complex matrices.
+    """Plan of a batched permanent (+ gradient) launch over packed complex
+    (``real=False``, complex128 data) or real (``real=True``, float64 data)
+    matrices.
 
     ``ks``: orders (1..32); ``offsets``: element offsets into the packed data
     (``workloads.pack`` produces both).  Owns the C plan and a workspace."""
 
-    def __init__(self, ks, offsets, want_grad: bool = True, device="cuda:0"):
+    def __init__(self, ks, offsets, want_grad: bool = True, device="cuda:0", real: bool = False):
         self.ks = np.ascontiguousarray(ks, dtype=np.int32)
         self.offsets = np.ascontiguousarray(offsets, dtype=np.int64)
         self.count = int(self.ks.size)
         self.want_grad = bool(want_grad)
         self.device = torch.device(device)
+        self.real = bool(real)
+        self.dtype = torch.float64 if self.real else torch.complex128
+        sfx = "_f64" if self.real else ""
+        self._run = getattr(N.lib(), "perm_batched" + sfx)
+        self._tune = getattr(N.lib(), "perm_batched_autotune" + sfx)
         h = ctypes.c_void_p()
-        N.check(N.lib().perm_batched_plan_create(self.count, self.ks.ctypes.data,
-                                                 self.offsets.ctypes.data, int(want_grad),
-                                                 ctypes.byref(h)), "perm_batched_plan_create")
+        N.check(getattr(N.lib(), "perm_batched_plan_create" + sfx)(
+            self.count, self.ks.ctypes.data, self.offsets.ctypes.data, int(want_grad),
+            ctypes.byref(h)), "perm_batched_plan_create" + sfx)
         self._h = h
         nb = int(N.lib().perm_batched_workspace_bytes(h))
         self.ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=self.device)
@@ -310,17 +317,17 @@ class BatchedPlan:
         self.close()
 
     def outputs(self, data: torch.Tensor):
-        out = torch.empty(self.count, dtype=torch.complex128, device=self.device)
+        out = torch.empty(self.count, dtype=self.dtype, device=self.device)
         grad = torch.empty_like(data) if self.want_grad else None
         return out, grad
 
     def run(self, data: torch.Tensor, out=None, grad=None, use_graph: bool = True):
-        if data.dtype != torch.complex128 or data.device != self.device or not data.is_contiguous():
-            raise ValueError("contiguous complex128 data on the plan's device expected")
+        if data.dtype != self.dtype or data.device != self.device or not data.is_contiguous():
+            raise ValueError(f"contiguous {self.dtype} data on the plan's device expected")
         if out is None:
             out, g2 = self.outputs(data)
             grad = g2 if grad is None else grad
-        st = N.lib().perm_batched(self._h, data.data_ptr(), out.data_ptr(),
+        st = self._run(self._h, data.data_ptr(), out.data_ptr(),
                                   grad.data_ptr() if grad is not None else None, int(use_graph),
                                   self.ws.data_ptr(), self.ws_bytes, _stream(self.device))
         N.check(st, "perm_batched")
@@ -329,7 +336,9 @@ class BatchedPlan:
     def autotune(self, data: torch.Tensor):
         out, grad = self.outputs(data)
         best = ctypes.c_double(0.0)
-        N.check(N.lib().perm_batched_autotune(self._h, data.data_ptr(), out.data_ptr(),
+        if data.dtype != self.dtype or data.device != self.device or not data.is_contiguous():
+            raise ValueError(f"contiguous {self.dtype} data on the plan's device expected")
+        N.check(self._tune(self._h, data.data_ptr(), out.data_ptr(),
                                               grad.data_ptr() if grad is not None else None,
                                               self.ws.data_ptr(), self.ws_bytes,
                                               _stream(self.device), ctypes.byref(best)),
@@ -414,40 +423,32 @@ def perm_sparse_decomp(n: int, col_ptr, row_idx, vals,
     device tensor."""
     device = torch.device(device)
     ks, ws, offs, data, _, folded = _decompose_arrays(n, col_ptr, row_idx, vals, flags, 0)
-    out = torch.zeros((), dtype=torch.complex128, device=device)
+    out = torch.zeros((), dtype=torch.float64, device=device)
     # the folded sum enters the weighted sum as two order-0 leaves (perm 1)
     fw = [float(f) for f in folded if f != 0.0]
     if len(ks) == 0 and not fw:
-        return out.real.clone()
+        return out
     dense_min = max(2, min(int(dense_min), 33))
     small = np.nonzero(ks < dense_min)[0]
     big = np.nonzero(ks >= dense_min)[0]
     order = np.concatenate([small, big])
-    perms = torch.zeros(len(ks) + len(fw), dtype=torch.complex128, device=device)
+    perms = torch.zeros(len(ks) + len(fw), dtype=torch.float64, device=device)
     perms[len(ks):] = 1.0
-    keep = []
-    if len(small):
-        # the batched kernels take complex entries: the small leaves' entries
-        # back to back
-        sizes = ks[small].astype(np.int64) ** 2
-        soff = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
-        packed = np.concatenate([data[offs[i]:offs[i] + sz] for i, sz in zip(small, sizes)])
-        d = torch.from_numpy(packed).to(device).to(torch.complex128)
-        plan = BatchedPlan(ks[small], soff, want_grad=False, device=device)
-        plan.run(d, out=perms[:len(small)], use_graph=False)
-        keep += [plan, d]
-    if len(big):  # one real sweep over the whole chip per large leaf
-        dev = torch.from_numpy(data).to(device)
-        keep.append(dev)
-        pv = perms.view(torch.float64)
-        for t, i in enumerate(big):
-            k = int(ks[i])
-            perm_dense_f64(dev[offs[i]:offs[i] + k * k].view(k, k), out=pv[2 * (len(small) + t)])
+    dev = torch.from_numpy(data).to(device)  # every leaf, one copy
+    keep = [dev]
+    if len(small):  # the small leaves in one batched launch, in place
+        plan = BatchedPlan(ks[small], offs[small], want_grad=False, device=device, real=True)
+        plan.run(dev, out=perms[:len(small)], use_graph=False)
+        keep.append(plan)
+    for t, i in enumerate(big):  # one real sweep over the whole chip per large leaf
+        k = int(ks[i])
+        perm_dense_f64(dev[offs[i]:offs[i] + k * k].view(k, k), out=perms[len(small) + t])
     w = torch.from_numpy(np.ascontiguousarray(np.concatenate([ws[order], fw]))).to(device)
-    N.check(N.lib().perm_weighted_sum(len(ks) + len(fw), w.data_ptr(), perms.data_ptr(),
-                                      out.data_ptr(), _stream(device)), "perm_weighted_sum")
+    N.check(N.lib().perm_weighted_sum_f64(len(ks) + len(fw), w.data_ptr(), perms.data_ptr(),
+                                          out.data_ptr(), _stream(device)),
+            "perm_weighted_sum_f64")
     torch.cuda.current_stream(device).synchronize()  # keep plan / weights alive until done
     for obj in keep:
         if isinstance(obj, BatchedPlan):
             obj.close()
-    return out.real.clone()
+    return out

@@ -46,10 +46,11 @@ struct BatchLaunch {
     double *stage = nullptr;
     dd *perm_parts = nullptr;
     dd *g_parts = nullptr;
-    const perm_c128 *data = nullptr;
-    perm_c128 *out = nullptr;
-    perm_c128 *grad = nullptr;
+    const double *data = nullptr;  // packed matrices: (re, im) pairs, or reals if `real`
+    double *out = nullptr;
+    double *grad = nullptr;
     int want_grad = 0;
+    int real = 0;
 };
 
 // Enqueues reset, staging, the persistent kernels (largest orders first) and
@@ -62,8 +63,9 @@ int launch_batched_forked(const BatchLaunch &L, hipStream_t stream,
                           const hipStream_t side[kBatchGroups], hipEvent_t fork,
                           const hipEvent_t join[kBatchGroups]);
 
-// out = sum_m wts[m] * perms[m] (double-double, fixed order).
-int launch_weighted_sum(int count, const double *wts, const perm_c128 *perms, perm_c128 *out,
+// out = sum_m wts[m] * perms[m] (double-double, fixed order); perms and out
+// are complex (re, im) pairs, or reals if `real`.
+int launch_weighted_sum(int count, const double *wts, const double *perms, double *out, bool real,
                         hipStream_t stream);
 
 }  // namespace perm

@@ -39,11 +39,13 @@ const int64_t kTuneGrid[kBatchGroups][3] = {{512, 1024, 2048}, {512, 768, 1024},
 struct TuneKey {
     int device = 0;
     int want_grad = 0;
+    int real = 0;
     std::array<int32_t, kBatchMaxK + 1> hist{};
     bool operator<(const TuneKey &o) const
     {
         if (device != o.device) return device < o.device;
         if (want_grad != o.want_grad) return want_grad < o.want_grad;
+        if (real != o.real) return real < o.real;
         return hist < o.hist;
     }
 };
@@ -59,6 +61,7 @@ std::map<TuneKey, TuneEntry> g_tune_cache;
 struct perm_plan {
     int count = 0;
     int want_grad = 0;
+    int real = 0;  // 1: real matrices (doubles), 0: complex (re, im) pairs
     std::vector<int32_t> k;
     std::vector<int64_t> off;
     BatchTuning tune;
@@ -95,6 +98,7 @@ size_t a256(size_t b) { return (b + 255) & ~size_t(255); }
 void derive(perm_plan &P)
 {
     const int ct = P.tune.log2_chunk;
+    const int64_t W = P.real ? 1 : 2;  // doubles per element
     P.mats.assign(P.count, BatchMatDev{});
     for (int g = 0; g < kBatchGroups; ++g) P.items[g].clear();
     int64_t item0 = 0, stage = 0, gdd = 0;
@@ -116,11 +120,11 @@ void derive(perm_plan &P)
             M.waves = int32_t(std::max<int64_t>(1, lanes / kWave));
         }
         M.stage = stage;
-        stage += 2 * int64_t(k) * batch_rows(k) + 2 * int64_t(batch_rows(k));
+        stage += W * int64_t(k) * batch_rows(k) + W * int64_t(batch_rows(k));
         M.item0 = item0;
         item0 += M.waves;
         M.gbase = gdd;
-        if (P.want_grad) gdd += int64_t(M.waves) * 2 * k * k;
+        if (P.want_grad) gdd += int64_t(M.waves) * W * k * k;
     }
     // Work list per group: largest order first (longest items first), then
     // matrix, then wave -- a fixed order, so the plan is deterministic.
@@ -188,6 +192,7 @@ TuneKey tune_key(const perm_plan &P)
     TuneKey key;
     hipGetDevice(&key.device);
     key.want_grad = P.want_grad;
+    key.real = P.real;
     for (int k : P.k) key.hist[k]++;
     return key;
 }
@@ -211,8 +216,8 @@ int ensure_streams(perm_plan &P)
     return PERM_OK;
 }
 
-BatchLaunch make_launch(const perm_plan &P, char *ws, const perm_c128 *data, perm_c128 *out,
-                        perm_c128 *grad)
+BatchLaunch make_launch(const perm_plan &P, char *ws, const double *data, double *out,
+                        double *grad)
 {
     BatchLaunch L;
     L.count = P.count;
@@ -230,15 +235,12 @@ BatchLaunch make_launch(const perm_plan &P, char *ws, const perm_c128 *data, per
     L.out = out;
     L.grad = grad;
     L.want_grad = P.want_grad;
+    L.real = P.real;
     return L;
 }
 
-}  // namespace
-
-extern "C" {
-
-int perm_batched_plan_create(int count, const int32_t *k, const int64_t *offset, int want_grad,
-                             perm_plan **plan)
+int plan_create(int count, const int32_t *k, const int64_t *offset, int want_grad, int real,
+                perm_plan **plan)
 {
     if (!plan) return PERM_EINVAL;
     *plan = nullptr;
@@ -249,6 +251,7 @@ int perm_batched_plan_create(int count, const int32_t *k, const int64_t *offset,
     if (!P) return PERM_EINVAL;
     P->count = count;
     P->want_grad = want_grad ? 1 : 0;
+    P->real = real;
     P->k.assign(k, k + count);
     P->off.assign(offset, offset + count);
     // the workspace must hold the largest layout over every tuning candidate:
@@ -271,27 +274,8 @@ int perm_batched_plan_create(int count, const int32_t *k, const int64_t *offset,
     return PERM_OK;
 }
 
-void perm_plan_destroy(perm_plan *plan)
-{
-    if (!plan) return;
-    // No plan-owned object is released while a graph launch that uses it is
-    // still queued or running: drop_graph waits for the last launch first,
-    // and the side streams (used only while capturing) are idle after it.
-    drop_graph(*plan);
-    if (plan->launched) hipEventDestroy(plan->launched);
-    for (int g = 0; g < kBatchGroups; ++g) {
-        if (plan->side[g]) hipStreamDestroy(plan->side[g]);
-        if (plan->join[g]) hipEventDestroy(plan->join[g]);
-    }
-    if (plan->capture) hipStreamDestroy(plan->capture);
-    if (plan->fork) hipEventDestroy(plan->fork);
-    delete plan;
-}
-
-size_t perm_batched_workspace_bytes(const perm_plan *plan) { return plan ? plan->ws_max : 0; }
-
-int perm_batched(perm_plan *plan, const perm_c128 *data, perm_c128 *out, perm_c128 *grad,
-                 int use_graph, void *ws, size_t ws_bytes, void *stream)
+int run_batched(perm_plan *plan, const double *data, double *out, double *grad, int use_graph,
+                void *ws, size_t ws_bytes, void *stream)
 {
     if (!plan || !data || !out) return PERM_EINVAL;
     if (plan->want_grad && !grad) return PERM_EINVAL;
@@ -331,9 +315,8 @@ int perm_batched(perm_plan *plan, const perm_c128 *data, perm_c128 *out, perm_c1
     return hipEventRecord(P.launched, st) == hipSuccess ? PERM_OK : PERM_EHIP;
 }
 
-int perm_batched_autotune(perm_plan *plan, const perm_c128 *data, perm_c128 *out,
-                          perm_c128 *grad, void *ws, size_t ws_bytes, void *stream,
-                          double *best_ms)
+int autotune(perm_plan *plan, const double *data, double *out, double *grad, void *ws,
+             size_t ws_bytes, void *stream, double *best_ms)
 {
     if (!plan || !data || !out) return PERM_EINVAL;
     if (plan->want_grad && !grad) return PERM_EINVAL;
@@ -368,11 +351,11 @@ int perm_batched_autotune(perm_plan *plan, const perm_c128 *data, perm_c128 *out
         P.tune = t;
         derive(P);
         P.uploaded_ws = nullptr;
-        int r = perm_batched(plan, data, out, grad, 1, ws, ws_bytes, stream);
+        int r = run_batched(plan, data, out, grad, 1, ws, ws_bytes, stream);
         if (r != PERM_OK) return r;
         if (hipEventRecord(e0, st) != hipSuccess) return PERM_EHIP;
         for (int rep = 0; rep < 2; ++rep)
-            if ((r = perm_batched(plan, data, out, grad, 1, ws, ws_bytes, stream)) != PERM_OK) return r;
+            if ((r = run_batched(plan, data, out, grad, 1, ws, ws_bytes, stream)) != PERM_OK) return r;
         if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
             return PERM_EHIP;
         hipEventElapsedTime(&ms, e0, e1);
@@ -424,11 +407,87 @@ int perm_batched_autotune(perm_plan *plan, const perm_c128 *data, perm_c128 *out
     return rc;
 }
 
+}  // namespace
+
+extern "C" {
+
+int perm_batched_plan_create(int count, const int32_t *k, const int64_t *offset, int want_grad,
+                             perm_plan **plan)
+{
+    return plan_create(count, k, offset, want_grad, 0, plan);
+}
+
+int perm_batched_plan_create_f64(int count, const int32_t *k, const int64_t *offset,
+                                 int want_grad, perm_plan **plan)
+{
+    return plan_create(count, k, offset, want_grad, 1, plan);
+}
+
+void perm_plan_destroy(perm_plan *plan)
+{
+    if (!plan) return;
+    // No plan-owned object is released while a graph launch that uses it is
+    // still queued or running: drop_graph waits for the last launch first,
+    // and the side streams (used only while capturing) are idle after it.
+    drop_graph(*plan);
+    if (plan->launched) hipEventDestroy(plan->launched);
+    for (int g = 0; g < kBatchGroups; ++g) {
+        if (plan->side[g]) hipStreamDestroy(plan->side[g]);
+        if (plan->join[g]) hipEventDestroy(plan->join[g]);
+    }
+    if (plan->capture) hipStreamDestroy(plan->capture);
+    if (plan->fork) hipEventDestroy(plan->fork);
+    delete plan;
+}
+
+size_t perm_batched_workspace_bytes(const perm_plan *plan) { return plan ? plan->ws_max : 0; }
+
+int perm_batched(perm_plan *plan, const perm_c128 *data, perm_c128 *out, perm_c128 *grad,
+                 int use_graph, void *ws, size_t ws_bytes, void *stream)
+{
+    if (plan && plan->real) return PERM_EINVAL;
+    return run_batched(plan, reinterpret_cast<const double *>(data),
+                       reinterpret_cast<double *>(out), reinterpret_cast<double *>(grad),
+                       use_graph, ws, ws_bytes, stream);
+}
+
+int perm_batched_f64(perm_plan *plan, const double *data, double *out, double *grad,
+                     int use_graph, void *ws, size_t ws_bytes, void *stream)
+{
+    if (plan && !plan->real) return PERM_EINVAL;
+    return run_batched(plan, data, out, grad, use_graph, ws, ws_bytes, stream);
+}
+
+int perm_batched_autotune(perm_plan *plan, const perm_c128 *data, perm_c128 *out,
+                          perm_c128 *grad, void *ws, size_t ws_bytes, void *stream,
+                          double *best_ms)
+{
+    if (plan && plan->real) return PERM_EINVAL;
+    return autotune(plan, reinterpret_cast<const double *>(data), reinterpret_cast<double *>(out),
+                    reinterpret_cast<double *>(grad), ws, ws_bytes, stream, best_ms);
+}
+
+int perm_batched_autotune_f64(perm_plan *plan, const double *data, double *out, double *grad,
+                              void *ws, size_t ws_bytes, void *stream, double *best_ms)
+{
+    if (plan && !plan->real) return PERM_EINVAL;
+    return autotune(plan, data, out, grad, ws, ws_bytes, stream, best_ms);
+}
+
 int perm_weighted_sum(int count, const double *weights, const perm_c128 *perms, perm_c128 *out,
                       void *stream)
 {
     if (count < 1 || !weights || !perms || !out) return PERM_EINVAL;
-    return launch_weighted_sum(count, weights, perms, out, static_cast<hipStream_t>(stream));
+    return launch_weighted_sum(count, weights, reinterpret_cast<const double *>(perms),
+                               reinterpret_cast<double *>(out), false,
+                               static_cast<hipStream_t>(stream));
+}
+
+int perm_weighted_sum_f64(int count, const double *weights, const double *perms, double *out,
+                          void *stream)
+{
+    if (count < 1 || !weights || !perms || !out) return PERM_EINVAL;
+    return launch_weighted_sum(count, weights, perms, out, true, static_cast<hipStream_t>(stream));
 }
 
 int perm_batched_plan_info(const perm_plan *plan, int64_t *n_items, int *log2_chunk,

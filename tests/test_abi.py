@@ -173,6 +173,34 @@ def test_batched_plan_errors_and_workspace():
     lib.perm_plan_destroy(h)
 
 
+def test_real_batched_plan_errors_and_workspace():
+    import ctypes
+    import numpy as np
+    lib = N.lib()
+    k = np.array([3, 24, 32], np.int32)
+    off = np.array([0, 9, 585], np.int64)
+    hc, hr = ctypes.c_void_p(), ctypes.c_void_p()
+    assert lib.perm_batched_plan_create(3, k.ctypes.data, off.ctypes.data, 1, ctypes.byref(hc)) == 0
+    assert lib.perm_batched_plan_create_f64(3, k.ctypes.data, off.ctypes.data, 1, ctypes.byref(hr)) == 0
+    nc, nr = lib.perm_batched_workspace_bytes(hc), lib.perm_batched_workspace_bytes(hr)
+    # one component instead of two: about half the staging and gradient partials
+    assert 0 < nr < nc
+    # each plan runs only through the entry points of its own element type
+    assert lib.perm_batched(hr, FAKE, FAKE, FAKE, 1, FAKE, nr, None) == N.PERM_EINVAL
+    assert lib.perm_batched_autotune(hr, FAKE, FAKE, FAKE, FAKE, nr, None, None) == N.PERM_EINVAL
+    assert lib.perm_batched_f64(hc, FAKE, FAKE, FAKE, 1, FAKE, nc, None) == N.PERM_EINVAL
+    assert lib.perm_batched_autotune_f64(hc, FAKE, FAKE, FAKE, FAKE, nc, None, None) == N.PERM_EINVAL
+    assert lib.perm_batched_f64(hr, FAKE, FAKE, FAKE, 1, FAKE, nr - 1, None) == N.PERM_EWORKSPACE
+    assert lib.perm_batched_f64(hr, FAKE, FAKE, None, 1, FAKE, nr, None) == N.PERM_EINVAL
+    k[1] = 33
+    h = ctypes.c_void_p()
+    assert lib.perm_batched_plan_create_f64(3, k.ctypes.data, off.ctypes.data, 0, ctypes.byref(h)) == N.PERM_EINVAL
+    assert lib.perm_weighted_sum_f64(0, FAKE, FAKE, FAKE, None) == N.PERM_EINVAL
+    assert lib.perm_weighted_sum_f64(2, FAKE, None, FAKE, None) == N.PERM_EINVAL
+    lib.perm_plan_destroy(hc)
+    lib.perm_plan_destroy(hr)
+
+
 def test_dense_ex_option_errors():
     import ctypes
     from paper_2502_16577_amd.api import PermOptions
