@@ -243,46 +243,26 @@ __device__ __forceinline__ void grad_item(const double *__restrict__ acol,
     // (-1)^g of the step (the walk takes steps in pairs, even then odd, so
     // it is known at compile time).
     //
-    // Rows are cut into NB blocks (independent dependency chains).  With
-    // pre_i the product of the earlier rows of i's block, P_b the product of
-    // block b, Q_b = P_0 ... P_{b-1}, F = P_0 ... P_{NB-1} the slice product
-    // and O the other slice's product, L_i = (-1)^g O (prod of the other
-    // blocks) pre_i (prod of the later rows of i's block).  The empty
-    // products (pre of a block's first row, Q_0) are never multiplied in:
-    // 3 (R - 1) complex products per lane and step in all.
+    // With pre_i = x_0 ... x_{i-1} (the earlier rows of the slice), F the
+    // slice product and O the other slice's product, L_i = (-1)^g O pre_i
+    // (prod of the later rows), formed from the last row down; the empty
+    // products (pre_0, the later rows of the last row) are never multiplied
+    // in: 3 (R - 1) complex products per lane and step.  One dependency
+    // chain: cutting the rows into independent chains (2, 3 or 4 of them)
+    // measured slower, as the extra partial products cost more in register
+    // pressure than the parallelism gains at two waves per SIMD.
     auto step = [&](uint32_t l, auto neg_tag) {
         constexpr bool NEG = decltype(neg_tag)::value;
         // the previous step's low-column values (written by this wave, in
         // order before these reads), unless this step opens a window
         const bool pend = want_grad && f > 0 && (l & fmask) != 0u;
-        // block b holds rows [b R / NB, (b + 1) R / NB): every block non-empty
-        constexpr int NB = R >= 8 ? 4 : (R >= 4 ? 2 : 1);
-        auto beg = [](int b) { return b * R / NB; };
-        double pr[R], pim[R];      // pre_i (unused for a block's first row)
-        double Pr[NB], Pi[NB];     // running block products, then P_b
+        double pr[R], pim[R];      // pre_i (i >= 1)
+        double fr = xr[0], fi = xi[0];
 #pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            Pr[b] = xr[beg(b)];
-            Pi[b] = xi[beg(b)];
-        }
-#pragma unroll
-        for (int t = 1; t < (R + NB - 1) / NB; ++t)
-#pragma unroll
-            for (int b = 0; b < NB; ++b) {
-                const int i = beg(b) + t;
-                if (i < beg(b + 1)) {
-                    pr[i] = Pr[b];
-                    pim[i] = Pi[b];
-                    gmul<CPLX>(Pr[b], Pi[b], xr[i], xi[i]);
-                }
-            }
-        double Qr[NB], Qi[NB];     // Q_b for b >= 1
-        double fr = Pr[0], fi = Pi[0];
-#pragma unroll
-        for (int b = 1; b < NB; ++b) {
-            Qr[b] = fr;
-            Qi[b] = fi;
-            gmul<CPLX>(fr, fi, Pr[b], Pi[b]);
+        for (int t = 1; t < R; ++t) {
+            pr[t] = fr;
+            pim[t] = fi;
+            gmul<CPLX>(fr, fi, xr[t], xi[t]);
         }
         // keeps the adds of the low-column reads after the product above
         __builtin_amdgcn_sched_barrier(0);
@@ -328,41 +308,24 @@ __device__ __forceinline__ void grad_item(const double *__restrict__ acol,
             if (CPLX) lo_add(1);
             lo_apply(l - 1);
         }
-        // E_b = (-1)^g O prod_{b' != b} P_b', formed from the last block down
-        double Er[NB], Ei[NB];
-        {
-            double tr = orr, ti = oii;
-#pragma unroll
-            for (int b = NB - 1; b >= 1; --b) {
-                Er[b] = Qr[b];
-                Ei[b] = Qi[b];
-                gmul<CPLX>(Er[b], Ei[b], tr, ti);
-                gmul<CPLX>(tr, ti, Pr[b], Pi[b]);
-            }
-            Er[0] = tr;
-            Ei[0] = ti;
-        }
-        // within each block from its last row: L_i = pre_i E_b (later rows);
-        // V goes to this wave's transposition buffer for the low columns
+        // from the last row down: s = (-1)^g O (prod of the later rows),
+        // L_i = pre_i s; V goes to this wave's transposition buffer for the
+        // low columns
+        double sufr = orr, sufi = oii;
         double *vr = vbuf + lane * STRIDE;
         double *vi = vbuf + (W - 1) * kWave * STRIDE + lane * STRIDE;
 #pragma unroll
-        for (int t = (R + NB - 1) / NB - 1; t >= 0; --t)
-#pragma unroll
-            for (int b = 0; b < NB; ++b) {
-                const int i = beg(b) + t;
-                if (i < beg(b + 1)) {
-                    double lr = Er[b], li = Ei[b];
-                    if (t > 0) {
-                        gmul<CPLX>(lr, li, pr[i], pim[i]);
-                        gmul<CPLX>(Er[b], Ei[b], xr[i], xi[i]);
-                    }
-                    wr[i] += lr;
-                    if (CPLX) wi[i] += li;
-                    vr[i] = lr;
-                    if (CPLX) vi[i] = li;
-                }
+        for (int t = R - 1; t >= 0; --t) {
+            double lr = sufr, li = sufi;
+            if (t > 0) {
+                gmul<CPLX>(lr, li, pr[t], pim[t]);
+                gmul<CPLX>(sufr, sufi, xr[t], xi[t]);
             }
+            wr[t] += lr;
+            if (CPLX) wi[t] += li;
+            vr[t] = lr;
+            if (CPLX) vi[t] = li;
+        }
     };
 
     auto close_window = [&](uint32_t l0) {
