@@ -342,12 +342,13 @@ int perm_batched_autotune_f64(perm_plan *plan, const double *data, double *out, 
 int perm_batched_plan_info(const perm_plan *plan, int64_t *n_items, int *log2_chunk,
                            int64_t *grid, int *tuned_from_cache);
 
-/* out = sum_m weights[m] * perms[m] over count >= 1 device values, in
- * double-double and a fixed order (used to combine the leaves of a
- * decomposition).  Asynchronous on `stream`. */
+/* out = sum_m weights[m] * perms[m] over count >= 1 complex device values
+ * (each product split exactly by FMA), in double-double and a fixed order.
+ * Asynchronous on `stream`. */
 int perm_weighted_sum(int count, const double *weights, const perm_c128 *perms, perm_c128 *out,
                       void *stream);
-/* The same over real values (double perms[count], double out[1]). */
+/* The same over real values (double perms[count], double out[1]); combines
+ * the leaves of a Section 4 decomposition, perm(A) = sum_l w_l perm(leaf_l). */
 int perm_weighted_sum_f64(int count, const double *weights, const double *perms, double *out,
                           void *stream);
 
