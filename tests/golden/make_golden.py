@@ -8,10 +8,10 @@ sha256 of its input so a test can refuse a value whose input drifted.  The
 script updates entries in place, so it can be rerun for a subset of names.
 """
 import json
-import math
 import os
 import sys
 import time
+from fractions import Fraction
 
 import numpy as np
 
