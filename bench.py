@@ -473,15 +473,17 @@ PAPER_TABLE3_GV100 = {35: {"DD": 1.40e-9, "Kahan": 8.78e-12, "DD_s": 1.31, "Kaha
 
 
 def _perm_long(api, A, acc, label):
-    """perm_dense_f64_ex of A; a sweep of more than 2^43 subset-steps runs as
-    groups of its launches (about 2^44 steps, under a minute, per group), with
-    one progress line per group."""
+    """perm_dense_f64_ex of A; a sweep of more than 2^43 subset-steps (2^40 in
+    the extended-precision walk, about eight times slower) runs as groups of
+    its launches (under a minute per group), with one progress line per
+    group."""
     import torch
     n = A.shape[0]
-    if n <= 44:
+    top = 41 if acc == api.ACC_EXTENDED else 44
+    if n <= top:
         return api.perm_dense_f64_ex(A, accumulation=acc).item()
     nl = api.dense_f64_launches(n, accumulation=acc)
-    group = max(1, nl >> (n - 1 - 44))
+    group = max(1, nl >> (n - 1 - top))
     ws = torch.empty(api.workspace_bytes(1, n), dtype=torch.uint8, device=A.device)
     out = torch.empty((), dtype=torch.float64, device=A.device)
     t0 = time.perf_counter()
@@ -513,17 +515,32 @@ def paper_tables(sizes):
         t0 = time.perf_counter()
         v = _perm_long(api, A, api.ACC_TWOSUM, f"table 4, n = {n}")
         dt = time.perf_counter() - t0
+        full = _golden("full_size.json")
+        g = full.get(f"u{n}")
+        want = g["value"][0] + g["value"][1] if g and g.get("digest") == workloads.digest(a) else None
+        rel = (lambda x: abs(x - want) / abs(want)) if want else (lambda x: None)
         print(_json({"table": 4, "n": n, "workload": f"dense {n}x{n} U[0,1) seed {1000 + n}",
                           "seconds": dt, "subset_steps_per_s": 2 ** (n - 1) / dt, "perm": v,
+                          "rel_error_vs_oracle": rel(v),
                           "paper_gv100_s": PAPER_TABLE4_GV100_S.get(n),
                           "paper_cpu44_s": PAPER_TABLE4_CPU44_S.get(n)}), flush=True)
+        if 13 <= n <= 48:  # the extended-precision walk on the same matrix
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            v = _perm_long(api, A, api.ACC_EXTENDED, f"table 4, n = {n}, extended")
+            dt = time.perf_counter() - t0
+            print(_json({"table": 4, "n": n, "accumulation": "extended", "seconds": dt,
+                              "subset_steps_per_s": 2 ** (n - 1) / dt, "perm": v,
+                              "rel_error_vs_oracle": rel(v)}), flush=True)
         if PAPER_TABLE3_GV100.get(n) is None:
             continue
         J = torch.full((n, n), 0.91, dtype=torch.float64, device=dev)
         # n! a^n in exact rational arithmetic for the stored double a = fl(0.91)
         exact = float(math.factorial(n) * fractions.Fraction(0.91) ** n)
-        for name, acc in (("twosum", api.ACC_TWOSUM), ("kahan", api.ACC_KAHAN),
-                          ("plain", api.ACC_PLAIN)):
+        modes = [("twosum", api.ACC_TWOSUM), ("kahan", api.ACC_KAHAN), ("plain", api.ACC_PLAIN)]
+        if 13 <= n <= 48:
+            modes.append(("extended", api.ACC_EXTENDED))
+        for name, acc in modes:
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             v = _perm_long(api, J, acc, f"table 3, n = {n}, {name}")

@@ -126,9 +126,18 @@ size_t perm_noalloc_scratch_bytes(void);
 #define PERM_ACC_TWOSUM 0  /* two-sum: the lane partial is a double-double ("DQ"); the default */
 #define PERM_ACC_PLAIN  1  /* plain double lane partial ("DD") */
 #define PERM_ACC_KAHAN  2  /* Kahan-compensated lane partial ("Kahan") */
+/* Extended precision, beyond the paper's modes: x, every product and the lane
+ * partial in double-double (two-sum updates of x, FMA products), about 2^-104
+ * per operation instead of 2^-53 and about eight times the work.  For deep
+ * cancellation, where R(A) / |perm(A)| is large (about 1e6 for U[0,1) entries
+ * at n = 40).  Orders 13..48 (PERM_EUNSUPPORTED otherwise; n = 0 gives 1);
+ * log2_lanes, log2_reseed and the split launches apply as in the other
+ * modes.  The staged copies and the workspace are those of the other modes. */
+#define PERM_ACC_EXTENDED 3
 
 typedef struct {
-    int accumulation;              /* PERM_ACC_TWOSUM, PERM_ACC_PLAIN or PERM_ACC_KAHAN */
+    int accumulation;              /* PERM_ACC_TWOSUM, PERM_ACC_PLAIN, PERM_ACC_KAHAN or
+                                      PERM_ACC_EXTENDED */
     int log2_reseed;               /* exact re-seed of x every 2^r steps; 0 = default (2^9),
                                       values above the lane's chunk mean once per chunk;
                                       steps are walked in blocks of 16 (8 for n = 13), so
@@ -149,7 +158,8 @@ typedef struct {
 
 /* perm_dense_f64 with options (opt may be NULL).  PERM_EINVAL for an unknown
  * accumulation mode, negative fields, or first_launch at or beyond the number
- * of launches.  A long sweep can be run as several calls, each over a range
+ * of launches; PERM_EUNSUPPORTED for PERM_ACC_EXTENDED outside orders 13..48
+ * (n = 0 gives 1).  A long sweep can be run as several calls, each over a range
  * of its launches (perm_dense_f64_launches gives their number), in order,
  * with the same A, options (apart from the range), workspace and stream: a
  * call adds its launches' block sums to the partials the earlier calls left

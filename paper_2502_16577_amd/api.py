@@ -67,6 +67,7 @@ class PermOptions(ctypes.Structure):
 ACC_TWOSUM = 0
 ACC_PLAIN = 1
 ACC_KAHAN = 2
+ACC_EXTENDED = 3  # x, products and lane sums in double-double (orders 13..48)
 
 
 def perm_dense_f64_ex(A: torch.Tensor, accumulation: int = ACC_TWOSUM, log2_reseed: int = 0,
@@ -76,7 +77,8 @@ def perm_dense_f64_ex(A: torch.Tensor, accumulation: int = ACC_TWOSUM, log2_rese
     """perm_dense_f64 with options: accumulation ACC_TWOSUM (default) or
     ACC_PLAIN (the paper's plain-double "DD" variant), the exact re-seed
     interval 2^log2_reseed (0 = default) and the longest single launch.
-    ACC_KAHAN selects Kahan-compensated lane sums (the paper's "Kahan").
+    ACC_KAHAN selects Kahan-compensated lane sums (the paper's "Kahan");
+    ACC_EXTENDED walks x and forms the products in double-double.
     first_launch / launch_count run part of a split sweep: calls over
     consecutive ranges of its launches (dense_f64_launches), in order and with
     the same ws, leave the permanent in out after the last one."""

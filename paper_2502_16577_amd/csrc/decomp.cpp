@@ -235,6 +235,8 @@ struct DDSum {
     }
     void add_product(double a, double b)
     {
+#pragma clang fp contract(off)
+        // (p must stay the rounded product: its error is added separately)
         const double p = a * b;
         add(p);
         add(std::fma(a, b, -p));

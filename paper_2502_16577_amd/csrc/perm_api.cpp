@@ -122,7 +122,8 @@ uint64_t host_prime(int k) { return kBinaryPrimes[k]; }
 
 using namespace perm;
 
-static_assert(kAccTwoSum == PERM_ACC_TWOSUM && kAccPlain == PERM_ACC_PLAIN && kAccKahan == PERM_ACC_KAHAN,
+static_assert(kAccTwoSum == PERM_ACC_TWOSUM && kAccPlain == PERM_ACC_PLAIN && kAccKahan == PERM_ACC_KAHAN &&
+                  kAccExtended == PERM_ACC_EXTENDED,
               "accumulation modes must match the ABI");
 
 namespace {
@@ -246,7 +247,7 @@ static bool sweep_options(int n, const perm_options *opt, SweepOptions &o)
     o = default_sweep_options(n);
     if (!opt) return true;
     if (opt->accumulation != PERM_ACC_TWOSUM && opt->accumulation != PERM_ACC_PLAIN &&
-        opt->accumulation != PERM_ACC_KAHAN)
+        opt->accumulation != PERM_ACC_KAHAN && opt->accumulation != PERM_ACC_EXTENDED)
         return false;
     if (opt->log2_reseed < 0 || opt->log2_reseed > 62 || opt->max_steps_per_launch < 0 ||
         opt->log2_lanes < 0 || opt->log2_lanes > 40 || opt->first_launch < 0 ||
@@ -276,6 +277,8 @@ int perm_dense_f64_ex(int n, const double *A, int64_t lda, const perm_options *o
     if (n > 0 && (!A || lda < n)) return PERM_EINVAL;
     SweepOptions o;
     if (!sweep_options(n, opt, o)) return PERM_EINVAL;
+    if (o.accumulation == kAccExtended && n > 0 && (n < kExtMinN || n > kExtMaxN))
+        return PERM_EUNSUPPORTED;
     if (o.first_launch >= (n == 0 ? 1 : dense_f64_launches(n, o))) return PERM_EINVAL;
     const int w = check_ws(ws, ws_bytes, perm_workspace_bytes(PERM_KIND_DENSE_F64, n, 0));
     if (w != PERM_OK) return w;

@@ -65,6 +65,8 @@ inline BinaryPrimes binary_primes()
 
 // Run-time options of the dense real sweep.
 constexpr int kAccTwoSum = 0, kAccPlain = 1, kAccKahan = 2;  // lane accumulation modes
+constexpr int kAccExtended = 3;  // x, products and lane partial in double-double
+constexpr int kExtMinN = 13, kExtMaxN = 48;  // orders of the extended-precision walk
 
 struct SweepOptions {
     int accumulation = kAccTwoSum;                  // kAcc* (same values as PERM_ACC_*)

@@ -194,6 +194,9 @@ __global__ __launch_bounds__(kBlock) void weighted_sum(int count, const double *
     for (int q = 0; q < W; ++q) {
         dd acc = dd{0.0, 0.0};
         for (int m = threadIdx.x; m < count; m += kBlock) {
+#pragma clang fp contract(off)
+            // (no contraction: fused into the sum below, p would enter as the
+            // exact product, whose rounding error e already carries)
             const double v = perms[W * m + q];
             const double p = wts[m] * v;
             const double e = __builtin_fma(wts[m], v, -p);  // exact product error

@@ -174,6 +174,195 @@ __global__ __launch_bounds__(kBlock) void sweep_dense_f64(const double *__restri
     if (threadIdx.x == 0) partials[blockIdx.x] = accumulate ? dd_add(partials[blockIdx.x], t) : t;
 }
 
+int64_t dense_launch_span(int n, const SweepPlan &p, const SweepOptions &o);
+
+// ---------------------------------------------------------------------------
+// Extended-precision walk (accumulation mode kAccExtended).  The FP64 walk
+// rounds every x_i and every product to 2^-53; where the alternating sum
+// cancels deeply (R(A) / |perm(A)| about 1e6 for U[0,1) entries at n = 40)
+// those roundings, which are correlated along the Gray walk, leave a
+// relative error near 1e-10 even when x is rebuilt exactly every 16 steps.
+// Here every x_i is a double-double (hi, lo) updated by two-sum, every
+// product a double-double formed with FMA and renormalised by two-sum, and
+// the lane partial a double-double, so each operation is exact to about
+// 2^-104 of its operands.  About eight times the FP64 walk's work; one step
+// per loop iteration; the lane partitioning, re-seeds and split launches are
+// those of the FP64 walk.  x0's low parts are staged in the negated-column
+// region, which this mode does not read.
+
+__global__ __launch_bounds__(kBlock) void prep_dense_ext(int n, const double *__restrict__ A,
+                                                         int64_t lda, double *__restrict__ acol,
+                                                         double *__restrict__ x0h,
+                                                         double *__restrict__ x0l)
+{
+    for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+        const int j = idx / n;
+        const int i = idx - j * n;
+        acol[idx] = A[int64_t(i) * lda + j];
+    }
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        double s = 0.0, e = 0.0;  // compensated row sum r_i = s + e
+        for (int j = 0; j < n; ++j) acc_add(s, e, A[int64_t(i) * lda + j]);
+        // x0_i = a_{i,n-1} - r_i / 2 as a double-double (halving is exact)
+        double h, l;
+        two_sum(A[int64_t(i) * lda + n - 1], -0.5 * s, h, l);
+        two_sum(h, l - 0.5 * e, x0h[i], x0l[i]);
+    }
+}
+
+// (ah, al) *= (bh, bl): the exact product of the high parts by FMA, the
+// cross terms, and a two-sum renormalisation (safe when a high part has
+// cancelled below its low part).  Contraction is off: fused into the
+// renormalising sum, the rounded product p would enter as the exact product,
+// whose rounding error e already carries, so that error would count twice.
+__device__ __forceinline__ void ext_mul(double &ah, double &al, double bh, double bl)
+{
+#pragma clang fp contract(off)
+    const double p = ah * bh;
+    double e = __builtin_fma(ah, bh, -p);
+    e = __builtin_fma(ah, bl, e);
+    e = __builtin_fma(al, bh, e);
+    const double s = p + e;
+    const double bb = s - p;
+    al = (p - (s - bb)) + (e - bb);
+    ah = s;
+}
+
+// x_i += v a_ij (v = +1 or -1): the rounding error of the high part goes to
+// the low part.
+template <int N>
+__device__ __forceinline__ void ext_add_column(double (&xh)[N], double (&xl)[N],
+                                               const double *__restrict__ a, double v)
+{
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        double s, t;
+        two_sum(xh[i], v * a[i], s, t);
+        xh[i] = s;
+        xl[i] += t;
+    }
+}
+
+template <int N>
+__device__ __forceinline__ void ext_reseed(double (&xh)[N], double (&xl)[N],
+                                           const double *__restrict__ acol,
+                                           const double *__restrict__ x0h,
+                                           const double *__restrict__ x0l, uint64_t hbits,
+                                           uint32_t low, int c)
+{
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        xh[i] = x0h[i];
+        xl[i] = x0l[i];
+    }
+    for (int j = c; j < N - 1; ++j) {
+        const double f = ((hbits >> (j - c)) & 1u) ? 1.0 : 0.0;
+        ext_add_column<N>(xh, xl, acol + j * N, f);  // adds 0 for columns not in the set
+    }
+    while (low) {
+        const int j = __builtin_ctz(low);
+        low &= low - 1u;
+        ext_add_column<N>(xh, xl, acol + j * N, 1.0);
+    }
+}
+
+// prod_i x_i as four interleaved double-double chains.
+template <int N>
+__device__ __forceinline__ void ext_product(const double (&xh)[N], const double (&xl)[N],
+                                            double &ph, double &pl)
+{
+    static_assert(N >= 4, "ext_product needs N >= 4");
+    double h[4], l[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        h[q] = xh[q];
+        l[q] = xl[q];
+    }
+#pragma unroll
+    for (int i = 4; i < N; ++i) ext_mul(h[i & 3], l[i & 3], xh[i], xl[i]);
+    ext_mul(h[0], l[0], h[1], l[1]);
+    ext_mul(h[2], l[2], h[3], l[3]);
+    ext_mul(h[0], l[0], h[2], l[2]);
+    ph = h[0];
+    pl = l[0];
+}
+
+template <int N>
+__global__ __launch_bounds__(kBlock) void sweep_dense_ext(const double *__restrict__ acol,
+                                                          const double *__restrict__ x0h,
+                                                          const double *__restrict__ x0l,
+                                                          dd *__restrict__ partials, int c, int r,
+                                                          uint32_t l_begin, uint32_t l_end,
+                                                          int accumulate)
+{
+    __shared__ dd red[kWavesPerBlock];
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t wave = uniform_wave_index();
+    const uint64_t K = lane_chunk_index(wave, lane);
+    const uint32_t kb = uint32_t(wave & 1u);
+    const uint64_t g0 = K << c;
+    const uint64_t hbits = (g0 ^ (g0 >> 1)) >> c;
+    const uint32_t rmask = (1u << r) - 1u;
+
+    double xh[N], xl[N];
+    double sh = 0.0, sl = 0.0;  // lane partial, double-double
+    for (uint32_t l = l_begin; l < l_end; ++l) {
+        if ((l & rmask) == 0) {
+            ext_reseed<N>(xh, xl, acol, x0h, x0l, hbits, gray_low(l, kb, c), c);
+        } else {
+            const int j = __builtin_ctz(l);
+            const bool add = (gray_low(l, kb, c) >> j) & 1u;
+            ext_add_column<N>(xh, xl, acol + j * N, add ? 1.0 : -1.0);
+        }
+        double ph, pl;
+        ext_product<N>(xh, xl, ph, pl);
+        if (l & 1u) {  // (-1)^g: g = K 2^c + l with c >= 1
+            ph = -ph;
+            pl = -pl;
+        }
+        double s, t;
+        two_sum(sh, ph, s, t);
+        two_sum(s, t + (sl + pl), sh, sl);
+    }
+    const dd tot = block_reduce_dd(dd{sh, sl}, red);
+    if (threadIdx.x == 0)
+        partials[blockIdx.x] = accumulate ? dd_add(partials[blockIdx.x], tot) : tot;
+}
+
+template <int N>
+static void launch_ext_n(const SweepPlan &p, const SweepOptions &o, const double *acol,
+                         const double *x0h, const double *x0l, dd *partials, hipStream_t stream)
+{
+    const int64_t C = int64_t(1) << p.log2_chunk;
+    const int64_t span = dense_launch_span(N, p, o);
+    const int64_t nl = C / span;
+    const int64_t first = std::min(o.first_launch, nl);
+    const int64_t end = o.launch_count > 0 ? std::min(nl, first + o.launch_count) : nl;
+    for (int64_t i = first; i < end; ++i) {
+        const int64_t l0 = i * span;
+        hipLaunchKernelGGL((sweep_dense_ext<N>), dim3(unsigned(p.blocks)), dim3(kBlock), 0, stream,
+                           acol, x0h, x0l, partials, p.log2_chunk, o.log2_reseed, uint32_t(l0),
+                           uint32_t(l0 + span), int(l0 > 0));
+    }
+}
+
+using ExtLauncher = void (*)(const SweepPlan &, const SweepOptions &, const double *,
+                             const double *, const double *, dd *, hipStream_t);
+
+template <int... Ns>
+struct ExtTable {
+    static ExtLauncher get(int n)
+    {
+        ExtLauncher f = nullptr;
+        ((n == Ns ? (f = &launch_ext_n<Ns>, 0) : 0), ...);
+        return f;
+    }
+};
+
+using DenseExtTable =
+    ExtTable<13, 14, 15, 16, 17, 18, 19, 20, 21, 22, 23, 24, 25, 26, 27, 28, 29, 30, 31, 32, 33,
+             34, 35, 36, 37, 38, 39, 40, 41, 42, 43, 44, 45, 46, 47, 48>;
+
 // Chunk steps per launch: the sweep runs over the full grid as consecutive
 // ranges of each lane's chunk of at most max_steps_per_launch subset-steps
 // per launch (one launch for the usual sizes); a power-of-two number of
@@ -296,6 +485,19 @@ int launch_dense_f64_opt(int n, const double *A, int64_t lda, double *out, const
     double *aneg = reinterpret_cast<double *>(ws + L.aneg);
     double *x0 = reinterpret_cast<double *>(ws + L.x0);
     dd *partials = reinterpret_cast<dd *>(ws + L.partials);
+    if (o.accumulation == kAccExtended) {
+        if (n < kExtMinN || n > kExtMaxN || p.log2_chunk < 1) return PERM_EUNSUPPORTED;
+        ExtLauncher f = DenseExtTable::get(n);
+        if (!f) return PERM_EUNSUPPORTED;
+        hipLaunchKernelGGL(prep_dense_ext, dim3(1), dim3(kBlock), 0, stream, n, A, lda, acol, x0,
+                           aneg);
+        SweepOptions oo = o;
+        if (oo.log2_reseed < 1 || oo.log2_reseed > p.log2_chunk) oo.log2_reseed = p.log2_chunk;
+        f(p, oo, acol, x0, aneg, partials, stream);
+        hipLaunchKernelGGL(finalize_partials, dim3(1), dim3(kBlock), 0, stream, partials, p.blocks,
+                           1, (n & 1) ? 2.0 : -2.0, out);
+        return hipGetLastError() == hipSuccess ? PERM_OK : PERM_EHIP;
+    }
     if (n <= kSmallN)  // one or a few waves: the gradient sweep's kernel without the gradient
         return launch_grad_or_small(n, false, A, lda, out, nullptr, false, ws, stream);
     hipLaunchKernelGGL(prep_dense_f64, dim3(1), dim3(kBlock), 0, stream, n, A, lda, acol, aneg, x0);

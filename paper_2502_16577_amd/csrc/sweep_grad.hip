@@ -181,7 +181,12 @@ using GradC128Table = GradTable<true, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14
                                 19, 20, 21, 22, 23, 24, 25, 26, 27, 28, 29, 30, 31, 32>;
 
 // Gray-walk decomposition of one matrix for grad_item: lanes * 2^c = 2^(n-1)
-// with c >= 1, at most 2^16 lanes (one wave per SIMD), r <= c - 1.
+// with c >= 1, at most 2^16 lanes (1024 two-wave items: two waves per SIMD),
+// r <= c - 1.  Below that cap the lanes are as many as keep 2^4 steps per
+// lane: more, shorter items fill the chip at small n, which outweighs their
+// per-item set-up (measured per perm_grad call: n = 16 complex 0.123 ->
+// 0.034 ms, n = 20 complex 0.146 -> 0.068 ms, n = 22 real 0.092 -> 0.064 ms
+// against the earlier minimum of 2^7 steps; n >= 24 sits at the cap).
 GradPlan plan_grad(int n)
 {
     GradPlan p;
@@ -193,7 +198,7 @@ GradPlan plan_grad(int n)
     const int total = n - 1;
     int lanes_log = total - 1;
     if (lanes_log > 16) lanes_log = 16;
-    if (total >= 12 && lanes_log > total - 7) lanes_log = total - 7;  // >= 128 steps per lane
+    if (total >= 12 && lanes_log > total - 4) lanes_log = total - 4;  // >= 16 steps per lane
     if (lanes_log < 0) lanes_log = 0;
     p.log2_chunk = total - lanes_log;
     p.log2_reseed = p.log2_chunk - 1 < 9 ? p.log2_chunk - 1 : 9;

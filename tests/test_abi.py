@@ -216,6 +216,16 @@ def test_dense_ex_option_errors():
     assert lib.perm_dense_f64_ex(20, FAKE, 20, ctypes.byref(bad), FAKE, FAKE, big, None) == N.PERM_EINVAL
     ok = PermOptions(1, 4, 1 << 20, 12)
     assert lib.perm_dense_f64_ex(20, FAKE, 20, ctypes.byref(ok), FAKE, None, 0, None) == N.PERM_EWORKSPACE
+    # the extended-precision walk: orders 13..48 only (checked before the
+    # workspace), n = 0 is the empty product as in every mode
+    ext = PermOptions(3, 0, 0, 0)
+    for n in (12, 49, 63):
+        assert lib.perm_dense_f64_ex(n, FAKE, n, ctypes.byref(ext), FAKE, FAKE, big, None) == N.PERM_EUNSUPPORTED
+    for n in (13, 48):
+        assert lib.perm_dense_f64_ex(n, FAKE, n, ctypes.byref(ext), FAKE, None, 0, None) == N.PERM_EWORKSPACE
+    assert lib.perm_dense_f64_launches(40, ctypes.byref(ext)) == 1
+    bad = PermOptions(4, 0, 0, 0)
+    assert lib.perm_dense_f64_ex(20, FAKE, 20, ctypes.byref(bad), FAKE, FAKE, big, None) == N.PERM_EINVAL
     # launch ranges: n = 26 (2^18 lanes of 128 steps) with 16-step re-seeds and
     # at most 2^22 subset-steps per launch is 8 launches; a range starting at
     # or beyond the last, or a negative field, is refused before any GPU work

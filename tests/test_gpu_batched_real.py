@@ -170,3 +170,34 @@ def test_weighted_sum_f64_exact_order():
     got = out.item()
     scale = float(np.sum(np.abs(w * p)))
     assert abs(got - want) <= 4 * U * abs(want) + 1e3 * U * U * scale, (got, want)
+
+
+@pytest.mark.parametrize("real", [True, False])
+def test_weighted_sum_keeps_product_rounding_errors(real):
+    # pairs w * p and 1 * (-fl(w p)): the exact sum is the sum of the
+    # products' rounding errors alone, which the double-double sum keeps (an
+    # FP64 sum returns noise; an error term counted twice doubles it)
+    from paper_2502_16577_amd import _native as N
+    rng = np.random.default_rng(161)
+    w = 1.0 + rng.random(400)
+    p = rng.standard_normal(400)
+    q = -(w * p)
+    wts = np.concatenate([w, np.ones(400)])
+    vals = np.concatenate([p, q])
+    exact = sum(Fraction(float(a)) * Fraction(float(b)) for a, b in zip(wts, vals))
+    assert exact != 0
+    wt = torch.from_numpy(wts).to(DEV)
+    if real:
+        pt = torch.from_numpy(vals).to(DEV)
+        out = torch.zeros((), dtype=torch.float64, device=DEV)
+        fn = N.lib().perm_weighted_sum_f64
+    else:  # the same values as real parts, their negatives as imaginary parts
+        pt = torch.from_numpy(vals - 1j * vals).to(DEV)
+        out = torch.zeros((), dtype=torch.complex128, device=DEV)
+        fn = N.lib().perm_weighted_sum
+    N.check(fn(len(vals), wt.data_ptr(), pt.data_ptr(), out.data_ptr(), api._stream(DEV)),
+            "weighted sum")
+    got = complex(out.item())
+    assert abs(Fraction(got.real) - exact) <= Fraction(1, 10 ** 12) * abs(exact), (got, float(exact))
+    if not real:
+        assert abs(Fraction(got.imag) + exact) <= Fraction(1, 10 ** 12) * abs(exact), (got, float(exact))
