@@ -430,6 +430,32 @@ def measure_rows():
                       "perm_err_over_tol": perr, "minor_err_over_tol": merr,
                       "tol": "perm 1e-13 R(A); minors 1e-10 perm(|minor|)",
                       "ok": bool(perr <= 1.0 and merr <= 1.0)}
+
+    # next-1: the paper's Table 4 shape at n = 40 (2^39 subset-steps) against
+    # the stored oracle value, in the default FP64 walk and the
+    # extended-precision walk (double-double x and products)
+    if "u40" in full:
+        n = 40
+        g = full["u40"]
+        a = workloads.uniform(n, 1000 + n)
+        assert workloads.digest(a) == g["digest"]
+        want = g["value"][0] + g["value"][1]
+        A = torch.from_numpy(a).to(dev)
+        out = torch.empty((), dtype=torch.float64, device=dev)
+        ws = torch.empty(api.workspace_bytes(1, n), dtype=torch.uint8, device=dev)
+        api.perm_dense_f64(A, out=out, ws=ws)
+        ms = _timed(lambda: api.perm_dense_f64(A, out=out, ws=ws), 1, st)
+        rel = abs(out.item() - want) / abs(want)
+        ms_ext = _timed(lambda: api.perm_dense_f64_ex(A, accumulation=api.ACC_EXTENDED, out=out,
+                                                      ws=ws), 1, st)
+        rel_ext = abs(out.item() - want) / abs(want)
+        fwd = n * 2.0 ** -53 * g["abs_sum"] / abs(want)
+        rows["next1_table4_n40"] = {
+            "workload": "dense 40x40 U[0,1) (seed 1040), 2^39 subset-steps",
+            "ms": ms, "rel_err": rel, "forward_error_scale": fwd, "ok_fp64": bool(rel <= fwd),
+            "extended_ms": ms_ext, "extended_rel_err": rel_ext, "tol": 1e-10,
+            "ok": bool(rel_ext <= 1e-10),
+            "paper_gv100_s": PAPER_TABLE4_GV100_S.get(n)}
     return rows
 
 
