@@ -362,27 +362,18 @@ def measure_rows():
                           "first_call_seconds": first, "exact": bool(str(val) == g["value"])}
         rows[name] = rec
 
-    # a8: sparse real, the 40x40 pattern with U[0,1) values (stored oracle
-    # value of Algorithm 2's CSC walk), else with entries d_i e_j (d, e
-    # uniform in [0.5, 1.5), seed 7040): perm = prod d prod e times the
-    # pattern's exact permanent
+    # a8: sparse real, the 40x40 pattern with entries d_i e_j (d, e uniform in
+    # [0.5, 1.5), seed 7040): perm = prod d prod e times the pattern's exact
+    # permanent; and, once its oracle value is stored, the same pattern with
+    # U[0,1) values (Algorithm 2's CSC walk in long double)
     n = 40
     pat = workloads.sparse_rows(n, 6, workloads.SEED_SPARSE40)
     assert workloads.digest(pat) == full["sparse40"]["digest"]
-    if "sparse40u" in full:
-        a = pat * workloads.uniform(n, workloads.SEED_SPARSE40_VALUES)
-        g = full["sparse40u"]
-        assert workloads.digest(a) == g["digest"]
-        values = "U[0,1) (seed 16585)"
-    else:
-        d, e = workloads.scaling_vectors(n, 7040)
-        a = pat * np.outer(d, e)
-        exact = fractions.Fraction(int(full["sparse40"]["value"]))
-        for v in list(d) + list(e):
-            exact *= fractions.Fraction(float(v))
-        g = {"value": [float(exact), 0.0]}
-        values = "d_i e_j, d and e uniform in [0.5, 1.5) (seed 7040)"
-    cp, ri, va = workloads.to_csc(a)
+    d, e = workloads.scaling_vectors(n, 7040)
+    exact = fractions.Fraction(int(full["sparse40"]["value"]))
+    for v in list(d) + list(e):
+        exact *= fractions.Fraction(float(v))
+    cp, ri, va = workloads.to_csc(pat * np.outer(d, e))
     out = torch.empty((), dtype=torch.float64, device=dev)
     wss = torch.empty(api.workspace_bytes(3, n, len(ri)), dtype=torch.uint8, device=dev)
     t0 = time.perf_counter()
@@ -390,16 +381,31 @@ def measure_rows():
     torch.cuda.synchronize()
     first = time.perf_counter() - t0
     ms = _timed(lambda: api.perm_sparse_f64(n, cp, ri, va, out=out, ws=wss), 3, st)
-    want = sum(g["value"])
+    want = float(exact)
     rel = abs(out.item() - want) / abs(want)
     ms_staged = _timed(lambda: api.perm_sparse_f64_staged(n, cp, ri, va, out=out, ws=wss), 1, st)
     rel_staged = abs(out.item() - want) / abs(want)
     rows["a8_sparse40"] = {
-        "workload": f"40x40 pattern with 6 per row (seed 16582), values {values}; "
-                    "perm_sparse_f64 (kernel generated for the pattern)",
+        "workload": "40x40 pattern with 6 per row (seed 16582), values d_i e_j, d and e uniform "
+                    "in [0.5, 1.5) (seed 7040); perm_sparse_f64 (kernel generated for the pattern)",
         "ms": ms, "first_call_seconds": first, "subset_steps_per_s": 2 ** (n - 1) / (ms * 1e-3),
         "rel_err": rel, "tol": 1e-10, "ok": bool(rel <= 1e-10),
         "staged_ms": ms_staged, "staged_rel_err": rel_staged}
+    if "sparse40u" in full:
+        g = full["sparse40u"]
+        a = pat * workloads.uniform(n, workloads.SEED_SPARSE40_VALUES)
+        assert workloads.digest(a) == g["digest"]
+        cp, ri, va = workloads.to_csc(a)
+        want = g["value"][0] + g["value"][1]
+        api.perm_sparse_f64(n, cp, ri, va, out=out, ws=wss)
+        rel_u = abs(out.item() - want) / abs(want)
+        api.perm_sparse_f64_staged(n, cp, ri, va, out=out, ws=wss)
+        rel_us = abs(out.item() - want) / abs(want)
+        rows["a8_sparse40"]["u_values"] = {
+            "workload": "the same pattern with U[0,1) values (seed 16585)",
+            "rel_err": rel_u, "staged_rel_err": rel_us,
+            "forward_error_scale": n * 2.0 ** -53 * g["abs_sum"] / abs(want),
+            "r_over_perm": g["abs_sum"] / abs(want)}
 
     # a10: perm + dperm/dA of one 24x24 matrix (complex and real)
     for name, key, mat in (("a10_grad24c", "grad24c", workloads.haar_block(120, 24, workloads.SEED_HAAR120)),

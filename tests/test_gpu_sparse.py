@@ -117,3 +117,26 @@ def test_full_size_sparse40_scaled_values(fn):
     want = scaled_perm(d, e, int(g["value"]))
     got = fn(40, cp, ri, v).item()
     assert abs(got - want) <= 1e-10 * want, (fn.__name__, got, want)
+
+
+def test_full_size_sparse40_u_values():
+    # the 40 x 40 pattern with U[0,1) values against the stored oracle value
+    # (Algorithm 2's CSC walk in long double, computed in resumable pieces):
+    # both FP64 sparse paths within the forward-error scale n u R(A) of FP64
+    # x and products, and the extended-precision walk (double-double x and
+    # products) on the same matrix held as dense within relative 1e-10
+    full = json.load(open(GOLDEN))
+    if "sparse40u" not in full:
+        pytest.skip("sparse40u: oracle value not stored yet (tests/golden/make_golden.py sparse40u)")
+    g = full["sparse40u"]
+    a = W.sparse_rows(40, 6, W.SEED_SPARSE40) * W.uniform(40, W.SEED_SPARSE40_VALUES)
+    assert W.digest(a) == g["digest"]
+    want = g["value"][0] + g["value"][1]
+    cp, ri, v = W.to_csc(a)
+    gate = 40 * 2.0 ** -53 * g["abs_sum"]
+    for fn in (api.perm_sparse_f64, api.perm_sparse_f64_staged):
+        got = fn(40, cp, ri, v).item()
+        assert abs(got - want) <= gate, (fn.__name__, got, want, abs(got - want) / abs(want))
+    A = torch.from_numpy(np.ascontiguousarray(a)).to(torch.device("cuda:0"))
+    got = api.perm_dense_f64_ex(A, accumulation=api.ACC_EXTENDED).item()
+    assert abs(got - want) <= 1e-10 * abs(want), (got, want, abs(got - want) / abs(want))
