@@ -528,51 +528,50 @@ def _perm_long(api, A, acc, label):
     return v
 
 
-def paper_tables(sizes):
+def paper_tables(sizes, tables=(3, 4), modes=None):
     """Table 4 shapes (dense U[0,1), one matrix per n) and Table 3 shapes (all
     entries 0.91, perm = n! 0.91^n, where the paper lists them) on this GPU;
-    one JSON line per row."""
+    one JSON line per row.  `tables` selects the tables and `modes` (names:
+    twosum, kahan, plain, extended; None for all) the accumulation modes."""
     import fractions
     import math
     import torch
     from paper_2502_16577_amd import api, workloads
 
     dev = torch.device("cuda:0")
+    all_modes = [("twosum", api.ACC_TWOSUM), ("kahan", api.ACC_KAHAN), ("plain", api.ACC_PLAIN),
+                 ("extended", api.ACC_EXTENDED)]
+    full = _golden("full_size.json")
     for n in sizes:
-        a = workloads.uniform(n, 1000 + n)
-        A = torch.from_numpy(a).to(dev)
-        if n <= 40:  # untimed first call (clocks, code loading); long sweeps need none
-            api.perm_dense_f64(A)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        v = _perm_long(api, A, api.ACC_TWOSUM, f"table 4, n = {n}")
-        dt = time.perf_counter() - t0
-        full = _golden("full_size.json")
-        g = full.get(f"u{n}")
-        want = g["value"][0] + g["value"][1] if g and g.get("digest") == workloads.digest(a) else None
-        rel = (lambda x: abs(x - want) / abs(want)) if want else (lambda x: None)
-        print(_json({"table": 4, "n": n, "workload": f"dense {n}x{n} U[0,1) seed {1000 + n}",
-                          "seconds": dt, "subset_steps_per_s": 2 ** (n - 1) / dt, "perm": v,
-                          "rel_error_vs_oracle": rel(v),
-                          "paper_gv100_s": PAPER_TABLE4_GV100_S.get(n),
-                          "paper_cpu44_s": PAPER_TABLE4_CPU44_S.get(n)}), flush=True)
-        if 13 <= n <= 48:  # the extended-precision walk on the same matrix
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            v = _perm_long(api, A, api.ACC_EXTENDED, f"table 4, n = {n}, extended")
-            dt = time.perf_counter() - t0
-            print(_json({"table": 4, "n": n, "accumulation": "extended", "seconds": dt,
-                              "subset_steps_per_s": 2 ** (n - 1) / dt, "perm": v,
-                              "rel_error_vs_oracle": rel(v)}), flush=True)
-        if PAPER_TABLE3_GV100.get(n) is None:
+        chosen = [(name, acc) for name, acc in all_modes
+                  if (modes is None or name in modes)
+                  and (acc != api.ACC_EXTENDED or 13 <= n <= 48)]
+        if 4 in tables:
+            a = workloads.uniform(n, 1000 + n)
+            A = torch.from_numpy(a).to(dev)
+            g = full.get(f"u{n}")
+            want = g["value"][0] + g["value"][1] if g and g.get("digest") == workloads.digest(a) else None
+            if n <= 40:  # untimed first call (clocks, code loading); long sweeps need none
+                api.perm_dense_f64(A)
+            for name, acc in chosen:
+                if acc in (api.ACC_KAHAN, api.ACC_PLAIN):
+                    continue  # Table 4 reports the default and the extended walk
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                v = _perm_long(api, A, acc, f"table 4, n = {n}, {name}")
+                dt = time.perf_counter() - t0
+                print(_json({"table": 4, "n": n, "accumulation": name,
+                                  "workload": f"dense {n}x{n} U[0,1) seed {1000 + n}",
+                                  "seconds": dt, "subset_steps_per_s": 2 ** (n - 1) / dt, "perm": v,
+                                  "rel_error_vs_oracle": abs(v - want) / abs(want) if want else None,
+                                  "paper_gv100_s": PAPER_TABLE4_GV100_S.get(n),
+                                  "paper_cpu44_s": PAPER_TABLE4_CPU44_S.get(n)}), flush=True)
+        if 3 not in tables or PAPER_TABLE3_GV100.get(n) is None:
             continue
         J = torch.full((n, n), 0.91, dtype=torch.float64, device=dev)
         # n! a^n in exact rational arithmetic for the stored double a = fl(0.91)
         exact = float(math.factorial(n) * fractions.Fraction(0.91) ** n)
-        modes = [("twosum", api.ACC_TWOSUM), ("kahan", api.ACC_KAHAN), ("plain", api.ACC_PLAIN)]
-        if 13 <= n <= 48:
-            modes.append(("extended", api.ACC_EXTENDED))
-        for name, acc in modes:
+        for name, acc in chosen:
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             v = _perm_long(api, J, acc, f"table 3, n = {n}, {name}")
@@ -593,6 +592,11 @@ def main():
     ap.add_argument("--no-rows", action="store_true", help="skip the other hot-path rows")
     ap.add_argument("--paper-tables", type=str, default="",
                     help="comma-separated n: time the paper's Table 4 / Table 3 shapes and exit")
+    ap.add_argument("--tables", type=str, default="3,4",
+                    help="with --paper-tables: which tables (comma-separated: 3, 4)")
+    ap.add_argument("--modes", type=str, default="",
+                    help="with --paper-tables: accumulation modes (twosum, kahan, plain, "
+                         "extended; default all)")
     ap.add_argument("--rows", action="store_true",
                     help="time the other hot-path rows (complex, sparse, binary, gradient) and exit")
     ap.add_argument("--only-batched", action="store_true",
@@ -620,7 +624,9 @@ def main():
                           "copy_bytes_written_per_launch": nbytes, "launches": 3}))
         return
     if args.paper_tables:
-        paper_tables([int(x) for x in args.paper_tables.split(",")])
+        paper_tables([int(x) for x in args.paper_tables.split(",")],
+                     tables=tuple(int(x) for x in args.tables.split(",")),
+                     modes=args.modes.split(",") if args.modes else None)
         return
     if args.rows:
         bench_rows()
