@@ -52,7 +52,7 @@ GOLDEN = os.path.join(ROOT, "tests", "golden")
 # plain 1 GiB copy (profiles/sweep_dense_f64_n32_u01.md).  Valid only for the
 # kernel source they were measured on; reported as null once it changes.
 COUNTERS_SRC = os.path.join(ROOT, "paper_2502_16577_amd", "csrc", "sweep_f64.hip")
-COUNTERS_SRC_SHA256 = "83a40bf7c5684fc647b774e18a7133a1130a54295c413c4d81f1d66160b75a05"
+COUNTERS_SRC_SHA256 = "85679f82f91b0d1042bd1a84a497f6a051faf1461ca215dfb9291f2b9ab63289"
 TRAFFIC_BYTES_PER_LAUNCH = 188 * 1024 * 2.000 + 32 * 1024 * 1.000
 
 
