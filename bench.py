@@ -401,9 +401,10 @@ def measure_rows():
         rel_u = abs(out.item() - want) / abs(want)
         api.perm_sparse_f64_staged(n, cp, ri, va, out=out, ws=wss)
         rel_us = abs(out.item() - want) / abs(want)
+        rel_ud = abs(api.perm_sparse_decomp(n, cp, ri, va).item() - want) / abs(want)
         rows["a8_sparse40"]["u_values"] = {
             "workload": "the same pattern with U[0,1) values (seed 16585)",
-            "rel_err": rel_u, "staged_rel_err": rel_us,
+            "rel_err": rel_u, "staged_rel_err": rel_us, "decomposition_rel_err": rel_ud,
             "forward_error_scale": n * 2.0 ** -53 * g["abs_sum"] / abs(want),
             "r_over_perm": g["abs_sum"] / abs(want)}
 
