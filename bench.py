@@ -52,8 +52,8 @@ GOLDEN = os.path.join(ROOT, "tests", "golden")
 # plain 1 GiB copy (profiles/sweep_dense_f64_n32_u01.md).  Valid only for the
 # kernel source they were measured on; reported as null once it changes.
 COUNTERS_SRC = os.path.join(ROOT, "paper_2502_16577_amd", "csrc", "sweep_f64.hip")
-COUNTERS_SRC_SHA256 = "85679f82f91b0d1042bd1a84a497f6a051faf1461ca215dfb9291f2b9ab63289"
-TRAFFIC_BYTES_PER_LAUNCH = 188 * 1024 * 2.000 + 32 * 1024 * 1.000
+COUNTERS_SRC_SHA256 = "860c755f3c21d87c2110505629d53395f6125ac00f223a9ce840f4878de4a77c"
+TRAFFIC_BYTES_PER_LAUNCH = 187.5 * 1024 * 2.000 + 32 * 1024 * 1.000
 
 
 def traffic_bytes():

@@ -183,10 +183,10 @@ int64_t dense_launch_span(int n, const SweepPlan &p, const SweepOptions &o);
 // those roundings, which are correlated along the Gray walk, leave a
 // relative error near 1e-10 even when x is rebuilt exactly every 16 steps.
 // Here every x_i is a double-double (hi, lo) updated by two-sum, every
-// product a double-double formed with FMA and renormalised by two-sum, and
-// the lane partial a double-double, so each operation is exact to about
-// 2^-104 of its operands.  About eight times the FP64 walk's work; one step
-// per loop iteration; the lane partitioning, re-seeds and split launches are
+// product a double-double formed with FMA, and the lane partial a
+// double-double, so each operation is exact to about 2^-104 of its
+// operands.  About six times the FP64 walk's time; one step per loop
+// iteration; the lane partitioning, re-seeds and split launches are
 // those of the FP64 walk.  x0's low parts are staged in the negated-column
 // region, which this mode does not read.
 
@@ -210,11 +210,14 @@ __global__ __launch_bounds__(kBlock) void prep_dense_ext(int n, const double *__
     }
 }
 
-// (ah, al) *= (bh, bl): the exact product of the high parts by FMA, the
-// cross terms, and a two-sum renormalisation (safe when a high part has
-// cancelled below its low part).  Contraction is off: fused into the
-// renormalising sum, the rounded product p would enter as the exact product,
-// whose rounding error e already carries, so that error would count twice.
+// (ah, al) *= (bh, bl): the rounded product of the high parts, and as the
+// low part its exact rounding error (FMA) plus the two cross terms.  The low
+// part is formed afresh at every factor, so it stays within a few ulps of
+// the high part and needs no renormalising sum; the pair holds the product
+// to about 2^-104 of the operands even where a high part has cancelled below
+// its low part.  Contraction is off: fused into a later sum, the rounded
+// product p would enter as the exact product, whose rounding error the low
+// part already carries, so that error would count twice.
 __device__ __forceinline__ void ext_mul(double &ah, double &al, double bh, double bl)
 {
 #pragma clang fp contract(off)
@@ -222,10 +225,8 @@ __device__ __forceinline__ void ext_mul(double &ah, double &al, double bh, doubl
     double e = __builtin_fma(ah, bh, -p);
     e = __builtin_fma(ah, bl, e);
     e = __builtin_fma(al, bh, e);
-    const double s = p + e;
-    const double bb = s - p;
-    al = (p - (s - bb)) + (e - bb);
-    ah = s;
+    ah = p;
+    al = e;
 }
 
 // x_i += v a_ij (v = +1 or -1): the rounding error of the high part goes to
