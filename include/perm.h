@@ -182,6 +182,17 @@ int64_t perm_dense_f64_launches(int n, const perm_options *opt);
 int perm_dense_c128(int n, const perm_c128 *A, int64_t lda, perm_c128 *out,
                     void *ws, size_t ws_bytes, void *stream);
 
+/* perm_dense_c128 with options (opt may be NULL for the default).  The
+ * complex sweep has two accumulation modes: PERM_ACC_TWOSUM (the default,
+ * as perm_dense_c128) and PERM_ACC_EXTENDED (real and imaginary parts of x,
+ * every product and the lane partial in double-double; orders 13..32, n = 0
+ * gives 1; log2_reseed applies).  PERM_ACC_PLAIN and PERM_ACC_KAHAN,
+ * log2_reseed in the default mode, and nonzero max_steps_per_launch,
+ * log2_lanes, first_launch or launch_count are PERM_EUNSUPPORTED; negative
+ * fields or an unknown mode PERM_EINVAL.  Same workspace as perm_dense_c128. */
+int perm_dense_c128_ex(int n, const perm_c128 *A, int64_t lda, const perm_options *opt,
+                       perm_c128 *out, void *ws, size_t ws_bytes, void *stream);
+
 /*
  * Permanent of a sparse real n x n matrix in CSC (Algorithm 2, SpaRyser,
  * Section 2.1): the same Gray walk as the dense sweep, but a step adds to x

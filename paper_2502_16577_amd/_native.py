@@ -58,6 +58,7 @@ SIGNATURES = [
     ("perm_batched", _int, [_vp, _vp, _vp, _vp, _int, _vp, _sz, _vp]),
     ("perm_batched_autotune", _int, [_vp, _vp, _vp, _vp, _vp, _sz, _vp, ctypes.POINTER(ctypes.c_double)]),
     ("perm_weighted_sum", _int, [_int, _vp, _vp, _vp, _vp]),
+    ("perm_dense_c128_ex", _int, [_int, _vp, _i64, _vp, _vp, _vp, _sz, _vp]),
     ("perm_batched_plan_create_f64", _int, [_int, _vp, _vp, _int, ctypes.POINTER(_vp)]),
     ("perm_batched_f64", _int, [_vp, _vp, _vp, _vp, _int, _vp, _sz, _vp]),
     ("perm_batched_autotune_f64", _int, [_vp, _vp, _vp, _vp, _vp, _sz, _vp, ctypes.POINTER(ctypes.c_double)]),

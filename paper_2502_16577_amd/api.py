@@ -122,6 +122,26 @@ def perm_dense_c128(A: torch.Tensor, out: torch.Tensor | None = None, ws=None) -
     return out
 
 
+def perm_dense_c128_ex(A: torch.Tensor, accumulation: int = ACC_TWOSUM, log2_reseed: int = 0,
+                       out: torch.Tensor | None = None, ws=None) -> torch.Tensor:
+    """perm_dense_c128 with an accumulation mode: ACC_TWOSUM (default) or
+    ACC_EXTENDED (x, products and lane sums in double-double; orders 13..32,
+    where log2_reseed sets the exact re-seed interval)."""
+    _check_square(A)
+    if A.dtype != torch.complex128:
+        raise TypeError("complex128 expected")
+    n = A.shape[0]
+    if out is None:
+        out = torch.empty((), dtype=torch.complex128, device=A.device)
+    ws, need = _workspace(N.KIND_DENSE_C128, n, 0, A.device, ws)
+    opt = PermOptions(accumulation, log2_reseed, 0, 0, 0, 0)
+    st = N.lib().perm_dense_c128_ex(n, A.data_ptr() if n else None, A.stride(0) if n else 0,
+                                    ctypes.byref(opt), out.data_ptr(), ws.data_ptr(), need,
+                                    _stream(A.device))
+    N.check(st, "perm_dense_c128_ex")
+    return out
+
+
 def _sparse_call(fn_name, n, col_ptr, row_idx, vals, device, out, ws):
     col_ptr = np.ascontiguousarray(col_ptr, dtype=np.int32)
     row_idx = np.ascontiguousarray(row_idx, dtype=np.int32)

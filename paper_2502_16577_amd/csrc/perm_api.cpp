@@ -297,6 +297,38 @@ int perm_dense_c128(int n, const perm_c128 *A, int64_t lda, perm_c128 *out, void
                              static_cast<hipStream_t>(stream));
 }
 
+int perm_dense_c128_ex(int n, const perm_c128 *A, int64_t lda, const perm_options *opt,
+                       perm_c128 *out, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!valid_n(n) || !out) return PERM_EINVAL;
+    if (n > 0 && (!A || lda < n)) return PERM_EINVAL;
+    int acc = PERM_ACC_TWOSUM, reseed = 0;
+    if (opt) {
+        if (opt->accumulation != PERM_ACC_TWOSUM && opt->accumulation != PERM_ACC_PLAIN &&
+            opt->accumulation != PERM_ACC_KAHAN && opt->accumulation != PERM_ACC_EXTENDED)
+            return PERM_EINVAL;
+        if (opt->log2_reseed < 0 || opt->log2_reseed > 62 || opt->max_steps_per_launch < 0 ||
+            opt->log2_lanes < 0 || opt->first_launch < 0 || opt->launch_count < 0)
+            return PERM_EINVAL;
+        acc = opt->accumulation;
+        reseed = opt->log2_reseed;
+        if (acc == PERM_ACC_PLAIN || acc == PERM_ACC_KAHAN) return PERM_EUNSUPPORTED;
+        if (acc == PERM_ACC_TWOSUM && reseed != 0) return PERM_EUNSUPPORTED;
+        if (opt->max_steps_per_launch != 0 || opt->log2_lanes != 0 || opt->first_launch != 0 ||
+            opt->launch_count != 0)
+            return PERM_EUNSUPPORTED;
+    }
+    if (acc == PERM_ACC_EXTENDED && n > 0 && (n < kExtMinN || n > kExtMaxNComplex))
+        return PERM_EUNSUPPORTED;
+    const int w = check_ws(ws, ws_bytes, perm_workspace_bytes(PERM_KIND_DENSE_C128, n, 0));
+    if (w != PERM_OK) return w;
+    if (acc == PERM_ACC_EXTENDED)
+        return launch_dense_c128_ext(n, A, lda, out, reseed, static_cast<char *>(ws),
+                                     static_cast<hipStream_t>(stream));
+    return launch_dense_c128(n, A, lda, out, static_cast<char *>(ws),
+                             static_cast<hipStream_t>(stream));
+}
+
 // A row or column without a nonzero value meets every permutation, so the
 // permanent is exactly 0 (the sweep's terms would cancel only to rounding).
 static bool has_empty_line(int n, const int32_t *col_ptr, const int32_t *row_idx,

@@ -223,6 +223,9 @@ int launch_dense_f64_opt(int n, const double *A, int64_t lda, double *out, const
 // sweep is split into (1 for n <= 12).
 SweepPlan dense_plan(int n, const SweepOptions &o);
 int64_t dense_f64_launches(int n, const SweepOptions &o);
+int launch_dense_c128_ext(int n, const perm_c128 *A, int64_t lda, perm_c128 *out,
+                          int log2_reseed, char *ws, hipStream_t stream);
+constexpr int kExtMaxNComplex = 32;  // orders of the complex extended-precision walk
 int launch_dense_c128(int n, const perm_c128 *A, int64_t lda, perm_c128 *out, char *ws,
                       hipStream_t stream);
 // Permanent and dperm/dA (row-major n x n, interleaved if complex).

@@ -248,7 +248,246 @@ using DenseC128Table =
                 33, 34, 35, 36, 37, 38, 39, 40, 41, 42, 43, 44, 45, 46, 47, 48, 49, 50, 51, 52, 53,
                 54, 55, 56, 57, 58, 59, 60, 61, 62, 63>;
 
+// ---------------------------------------------------------------------------
+// Extended-precision complex walk (accumulation mode kAccExtended): the real
+// and imaginary parts of every x_i are double-doubles updated by two-sum,
+// every factor of the product a complex double-double product (each real
+// product the rounded product of the high parts plus, as the low part, its
+// FMA rounding error and the cross terms; the two real sums by two-sum), and
+// the lane partial a complex double-double.  Each operation is then exact to
+// about 2^-104 of its operands.  One step per loop iteration; the lane
+// partitioning and re-seeds are those of the FP64 walk.  x0's low parts are
+// staged in the negated-column region, which this mode does not read.
+
+__global__ __launch_bounds__(kBlock) void prep_dense_c128_ext(int n, const perm_c128 *__restrict__ A,
+                                                              int64_t lda, double *__restrict__ acol,
+                                                              double *__restrict__ x0h,
+                                                              double *__restrict__ x0l)
+{
+    for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+        const int j = idx / n;
+        const int i = idx - j * n;
+        const perm_c128 v = A[int64_t(i) * lda + j];
+        acol[2 * idx] = v.re;
+        acol[2 * idx + 1] = v.im;
+    }
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        double sr = 0.0, er = 0.0, si = 0.0, ei = 0.0;  // compensated row sums
+        for (int j = 0; j < n; ++j) {
+            const perm_c128 v = A[int64_t(i) * lda + j];
+            acc_add(sr, er, v.re);
+            acc_add(si, ei, v.im);
+        }
+        // x0_i = a_{i,n-1} - r_i / 2 as a double-double per component
+        const perm_c128 last = A[int64_t(i) * lda + n - 1];
+        double h, l;
+        two_sum(last.re, -0.5 * sr, h, l);
+        two_sum(h, l - 0.5 * er, x0h[2 * i], x0l[2 * i]);
+        two_sum(last.im, -0.5 * si, h, l);
+        two_sum(h, l - 0.5 * ei, x0h[2 * i + 1], x0l[2 * i + 1]);
+    }
+}
+
+// a b as a double-double (rounded product of the high parts; its FMA
+// rounding error and the cross terms as the low part).  Contraction is off:
+// fused into a later sum, the rounded product would enter as the exact
+// product, whose rounding error the low part already carries.
+__device__ __forceinline__ void cext_prod(double ah, double al, double bh, double bl, double &h,
+                                          double &l)
+{
+#pragma clang fp contract(off)
+    h = ah * bh;
+    double e = __builtin_fma(ah, bh, -h);
+    e = __builtin_fma(ah, bl, e);
+    l = __builtin_fma(al, bh, e);
+}
+
+// (ar, ai) *= (br, bi), every component a double-double (high, low).  The
+// two sums are two-sums written out with contraction off and without
+// negating a product: a negated product in a contracting scope becomes a
+// new, contractible multiply that the compiler fuses into the sum, which
+// counts the product's rounding error twice.
+__device__ __forceinline__ void cext_mul(double &arh, double &arl, double &aih, double &ail,
+                                         double brh, double brl, double bih, double bil)
+{
+#pragma clang fp contract(off)
+    double p1h, p1l, p2h, p2l, p3h, p3l, p4h, p4l;
+    cext_prod(arh, arl, brh, brl, p1h, p1l);
+    cext_prod(aih, ail, bih, bil, p2h, p2l);
+    cext_prod(arh, arl, bih, bil, p3h, p3l);
+    cext_prod(aih, ail, brh, brl, p4h, p4l);
+    // re = p1 - p2
+    double s = p1h - p2h;
+    double bb = s - p1h;
+    double t = (p1h - (s - bb)) - (p2h + bb);
+    arh = s;
+    arl = t + (p1l - p2l);
+    // im = p3 + p4
+    s = p3h + p4h;
+    bb = s - p3h;
+    t = (p3h - (s - bb)) + (p4h - bb);
+    aih = s;
+    ail = t + (p3l + p4l);
+}
+
+// x_i += v a_ij for both components (v = +1 or -1, or 0 in a re-seed).
+template <int N>
+__device__ __forceinline__ void cext_add_column(double (&xrh)[N], double (&xrl)[N],
+                                                double (&xih)[N], double (&xil)[N],
+                                                const double *__restrict__ a, double v)
+{
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        double s, t;
+        two_sum(xrh[i], v * a[2 * i], s, t);
+        xrh[i] = s;
+        xrl[i] += t;
+        two_sum(xih[i], v * a[2 * i + 1], s, t);
+        xih[i] = s;
+        xil[i] += t;
+    }
+}
+
+template <int N>
+__global__ __launch_bounds__(kBlock) void sweep_dense_c128_ext(const double *__restrict__ acol,
+                                                               const double *__restrict__ x0h,
+                                                               const double *__restrict__ x0l,
+                                                               dd *__restrict__ partials, int c,
+                                                               int r, uint32_t l_begin,
+                                                               uint32_t l_end, int accumulate)
+{
+    __shared__ dd red[kWavesPerBlock];
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t wave = uniform_wave_index();
+    const uint64_t K = lane_chunk_index(wave, lane);
+    const uint32_t kb = uint32_t(wave & 1u);
+    const uint64_t g0 = K << c;
+    const uint64_t hbits = (g0 ^ (g0 >> 1)) >> c;
+    const uint32_t rmask = (1u << r) - 1u;
+
+    double xrh[N], xrl[N], xih[N], xil[N];
+    double srh = 0.0, srl = 0.0, sih = 0.0, sil = 0.0;  // lane partial
+    for (uint32_t l = l_begin; l < l_end; ++l) {
+        if ((l & rmask) == 0) {
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                xrh[i] = x0h[2 * i];
+                xrl[i] = x0l[2 * i];
+                xih[i] = x0h[2 * i + 1];
+                xil[i] = x0l[2 * i + 1];
+            }
+            for (int j = c; j < N - 1; ++j) {
+                const double f = ((hbits >> (j - c)) & 1u) ? 1.0 : 0.0;
+                cext_add_column<N>(xrh, xrl, xih, xil, acol + 2 * j * N, f);
+            }
+            uint32_t low = gray_low(l, kb, c);
+            while (low) {
+                const int j = __builtin_ctz(low);
+                low &= low - 1u;
+                cext_add_column<N>(xrh, xrl, xih, xil, acol + 2 * j * N, 1.0);
+            }
+        } else {
+            const int j = __builtin_ctz(l);
+            const bool add = (gray_low(l, kb, c) >> j) & 1u;
+            cext_add_column<N>(xrh, xrl, xih, xil, acol + 2 * j * N, add ? 1.0 : -1.0);
+        }
+        // the product as two interleaved chains
+        double prh[2], prl[2], pih[2], pil[2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            prh[q] = xrh[q];
+            prl[q] = xrl[q];
+            pih[q] = xih[q];
+            pil[q] = xil[q];
+        }
+#pragma unroll
+        for (int i = 2; i < N; ++i)
+            cext_mul(prh[i & 1], prl[i & 1], pih[i & 1], pil[i & 1], xrh[i], xrl[i], xih[i], xil[i]);
+        cext_mul(prh[0], prl[0], pih[0], pil[0], prh[1], prl[1], pih[1], pil[1]);
+        double th = prh[0], tl = prl[0], uh = pih[0], ul = pil[0];
+        if (l & 1u) {  // (-1)^g: g = K 2^c + l with c >= 1
+            th = -th;
+            tl = -tl;
+            uh = -uh;
+            ul = -ul;
+        }
+        double s, t;
+        two_sum(srh, th, s, t);
+        two_sum(s, t + (srl + tl), srh, srl);
+        two_sum(sih, uh, s, t);
+        two_sum(s, t + (sil + ul), sih, sil);
+    }
+    const dd tr = block_reduce_dd(dd{srh, srl}, red);
+    const dd ti = block_reduce_dd(dd{sih, sil}, red);
+    if (threadIdx.x == 0) {
+        dd *pp = partials + 2 * blockIdx.x;
+        pp[0] = accumulate ? dd_add(pp[0], tr) : tr;
+        pp[1] = accumulate ? dd_add(pp[1], ti) : ti;
+    }
+}
+
+template <int N>
+static void launch_csweep_ext_n(const SweepPlan &p, int log2_reseed, const double *acol,
+                                const double *x0h, const double *x0l, dd *partials,
+                                hipStream_t stream)
+{
+    // launches of at most 2^37 subset-steps (the walk is about 8 times slower
+    // than the FP64 one), each over a consecutive range of every lane's chunk
+    // starting on a re-seed boundary
+    const int64_t C = int64_t(1) << p.log2_chunk;
+    int64_t span = std::max<int64_t>((int64_t(1) << 37) / p.lanes, int64_t(1) << log2_reseed);
+    int64_t pow2 = 1;
+    while (pow2 * 2 <= span) pow2 *= 2;
+    span = std::min(pow2, C);
+    for (int64_t l0 = 0; l0 < C; l0 += span)
+        hipLaunchKernelGGL(sweep_dense_c128_ext<N>, dim3(unsigned(p.blocks)), dim3(kBlock), 0,
+                           stream, acol, x0h, x0l, partials, p.log2_chunk, log2_reseed,
+                           uint32_t(l0), uint32_t(l0 + span), int(l0 > 0));
+}
+
+using CExtLauncher = void (*)(const SweepPlan &, int, const double *, const double *,
+                              const double *, dd *, hipStream_t);
+
+template <int... Ns>
+struct CExtTable {
+    static CExtLauncher get(int n)
+    {
+        CExtLauncher f = nullptr;
+        ((n == Ns ? (f = &launch_csweep_ext_n<Ns>, 0) : 0), ...);
+        return f;
+    }
+};
+
+using DenseC128ExtTable = CExtTable<13, 14, 15, 16, 17, 18, 19, 20, 21, 22, 23, 24, 25, 26, 27, 28,
+                                    29, 30, 31, 32>;
+
 __global__ void write_one_c128(perm_c128 *out) { out[0] = perm_c128{1.0, 0.0}; }
+
+int launch_dense_c128_ext(int n, const perm_c128 *A, int64_t lda, perm_c128 *out,
+                          int log2_reseed, char *ws, hipStream_t stream)
+{
+    if (n == 0) {
+        hipLaunchKernelGGL(write_one_c128, dim3(1), dim3(1), 0, stream, out);
+        return hipGetLastError() == hipSuccess ? PERM_OK : PERM_EHIP;
+    }
+    CExtLauncher f = DenseC128ExtTable::get(n);
+    if (!f) return PERM_EUNSUPPORTED;
+    const SweepPlan p = plan_sweep(n, 0);
+    if (p.log2_chunk < 1) return PERM_EUNSUPPORTED;
+    int r = log2_reseed > 0 ? log2_reseed : p.log2_reseed;
+    if (r > p.log2_chunk) r = p.log2_chunk;
+    const DenseWs L = dense_ws_layout(n, 2, dense_ws_blocks(n));
+    double *acol = reinterpret_cast<double *>(ws + L.acol);
+    double *x0l = reinterpret_cast<double *>(ws + L.aneg);
+    double *x0h = reinterpret_cast<double *>(ws + L.x0);
+    dd *partials = reinterpret_cast<dd *>(ws + L.partials);
+    hipLaunchKernelGGL(prep_dense_c128_ext, dim3(1), dim3(kBlock), 0, stream, n, A, lda, acol, x0h,
+                       x0l);
+    f(p, r, acol, x0h, x0l, partials, stream);
+    hipLaunchKernelGGL(finalize_partials, dim3(1), dim3(kBlock), 0, stream, partials, p.blocks, 2,
+                       (n & 1) ? 2.0 : -2.0, reinterpret_cast<double *>(out));
+    return hipGetLastError() == hipSuccess ? PERM_OK : PERM_EHIP;
+}
 
 int launch_dense_c128(int n, const perm_c128 *A, int64_t lda, perm_c128 *out, char *ws,
                       hipStream_t stream)

@@ -226,6 +226,22 @@ def test_dense_ex_option_errors():
     assert lib.perm_dense_f64_launches(40, ctypes.byref(ext)) == 1
     bad = PermOptions(4, 0, 0, 0)
     assert lib.perm_dense_f64_ex(20, FAKE, 20, ctypes.byref(bad), FAKE, FAKE, big, None) == N.PERM_EINVAL
+    # the complex sweep: two-sum (default) and extended (orders 13..32) only
+    f = lib.perm_dense_c128_ex
+    for opt, want in ((PermOptions(1, 0, 0, 0), N.PERM_EUNSUPPORTED),
+                      (PermOptions(2, 0, 0, 0), N.PERM_EUNSUPPORTED),
+                      (PermOptions(0, 5, 0, 0), N.PERM_EUNSUPPORTED),
+                      (PermOptions(3, 0, 1 << 20, 0), N.PERM_EUNSUPPORTED),
+                      (PermOptions(3, 0, 0, 12), N.PERM_EUNSUPPORTED),
+                      (PermOptions(5, 0, 0, 0), N.PERM_EINVAL),
+                      (PermOptions(3, -1, 0, 0), N.PERM_EINVAL)):
+        assert f(20, FAKE, 20, ctypes.byref(opt), FAKE, FAKE, big, None) == want, (opt.accumulation,)
+    for n in (12, 33):
+        assert f(n, FAKE, n, ctypes.byref(ext), FAKE, FAKE, big, None) == N.PERM_EUNSUPPORTED
+    for n in (13, 32):
+        assert f(n, FAKE, n, ctypes.byref(ext), FAKE, None, 0, None) == N.PERM_EWORKSPACE
+    assert f(20, FAKE, 20, None, FAKE, None, 0, None) == N.PERM_EWORKSPACE
+    assert f(20, FAKE, 19, ctypes.byref(ext), FAKE, FAKE, big, None) == N.PERM_EINVAL
     # launch ranges: n = 26 (2^18 lanes of 128 steps) with 16-step re-seeds and
     # at most 2^22 subset-steps per launch is 8 launches; a range starting at
     # or beyond the last, or a negative field, is refused before any GPU work

@@ -352,3 +352,86 @@ def test_split_sweep_over_several_calls(oracle):
         assert out.item() == one, ranges
     want = oracle.ryser(a)
     assert abs(one - want) <= 1e-10 * abs(want)
+
+
+def _exact_perm_gaussian(m):
+    """Exact permanent of a matrix of Gaussian integers (re, im int pairs):
+    Ryser's formula over all subsets in Gray order, in Python integers."""
+    n = len(m)
+    rs = [[0, 0] for _ in range(n)]
+    tot_re = tot_im = 0
+    in_s = [False] * n
+    prev = 0
+    for g in range(1, 1 << n):
+        gray = g ^ (g >> 1)
+        j = (gray ^ prev).bit_length() - 1
+        prev = gray
+        sgn = 1 if not in_s[j] else -1
+        in_s[j] = not in_s[j]
+        for i in range(n):
+            rs[i][0] += sgn * m[i][j][0]
+            rs[i][1] += sgn * m[i][j][1]
+        pr, pi = 1, 0
+        for i in range(n):
+            pr, pi = pr * rs[i][0] - pi * rs[i][1], pr * rs[i][1] + pi * rs[i][0]
+        if bin(gray).count("1") & 1:
+            tot_re -= pr
+            tot_im -= pi
+        else:
+            tot_re += pr
+            tot_im += pi
+    s = -1 if n & 1 else 1
+    return s * tot_re, s * tot_im
+
+
+@pytest.mark.parametrize("n", [13, 16, 18])
+def test_complex_extended_gaussian_integers(n):
+    # entries a + bi with a, b in [-3, 3]: the exact permanent is a Gaussian
+    # integer beyond 2^53 at n >= 16, where the FP64 walk misses it by a
+    # fraction of a unit (n = 16) to a few units (n = 18); the extended walk is
+    # held to its double-double forward-error scale 2 n u^2 R(A) plus the final
+    # rounding (R(A) = 2 sum over the 2^(n-1) sign vectors of |prod x|)
+    rng = np.random.default_rng(1400 + n)
+    ints = rng.integers(-3, 4, size=(n, n, 2))
+    m = [[(int(ints[i, j, 0]), int(ints[i, j, 1])) for j in range(n)] for i in range(n)]
+    er, ei = _exact_perm_gaussian(m)
+    a = ints[..., 0] + 1j * ints[..., 1]
+    s = np.array([[1.0 if (g >> j) & 1 else -1.0 for j in range(n - 1)] + [1.0]
+                  for g in range(1 << (n - 1))])
+    r = 2.0 * float(np.sum(np.prod(np.abs(s @ a.T) / 2.0, axis=1)))
+    got = complex(api.perm_dense_c128_ex(torch.from_numpy(a).to(DEV),
+                                         accumulation=api.ACC_EXTENDED).cpu().item())
+    mod = math.hypot(er, ei)
+    gate = mod * 2.0 ** -52 + 2 * n * 2.0 ** -106 * r
+    assert abs(got.real - er) <= gate and abs(got.imag - ei) <= gate, (n, got, er, ei, r / mod)
+
+
+@pytest.mark.parametrize("n", [24, 30])
+def test_complex_extended_all_equal(n):
+    # every entry c: perm = n! c^n in exact rational arithmetic
+    c = complex(0.6, 0.5)
+    cr, ci = fractions.Fraction(c.real), fractions.Fraction(c.imag)
+    pr, pi = fractions.Fraction(1), fractions.Fraction(0)
+    for _ in range(n):
+        pr, pi = pr * cr - pi * ci, pr * ci + pi * cr
+    f = math.factorial(n)
+    er, ei = f * pr, f * pi
+    a = np.full((n, n), c)
+    got = complex(api.perm_dense_c128_ex(torch.from_numpy(a).to(DEV),
+                                         accumulation=api.ACC_EXTENDED).cpu().item())
+    mod = math.hypot(float(er), float(ei))
+    assert abs(fractions.Fraction(got.real) - er) <= fractions.Fraction(mod) * fractions.Fraction(1, 2 ** 51), (n, got)
+    assert abs(fractions.Fraction(got.imag) - ei) <= fractions.Fraction(mod) * fractions.Fraction(1, 2 ** 51), (n, got)
+
+
+@pytest.mark.parametrize("n", [14, 21, 27])
+def test_complex_extended_haar_vs_oracle(oracle, n):
+    # Haar blocks against the long-double oracle at the complex gate, and the
+    # default mode through the same entry point equal to perm_dense_c128
+    a = W.haar_block(2 * n, n, 1500 + n)
+    A = torch.from_numpy(a).to(DEV)
+    want, r = oracle.ryser(a, with_abs=True)
+    got = complex(api.perm_dense_c128_ex(A, accumulation=api.ACC_EXTENDED).cpu().item())
+    assert abs(got - want) <= 1e-13 * r, (n, got, want, r)
+    d = complex(api.perm_dense_c128_ex(A).cpu().item())
+    assert d == complex(api.perm_dense_c128(A).cpu().item())
