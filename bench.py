@@ -406,7 +406,8 @@ def measure_rows():
             "workload": "the same pattern with U[0,1) values (seed 16585)",
             "rel_err": rel_u, "staged_rel_err": rel_us, "decomposition_rel_err": rel_ud,
             "forward_error_scale": n * 2.0 ** -53 * g["abs_sum"] / abs(want),
-            "r_over_perm": g["abs_sum"] / abs(want)}
+            "r_over_perm": g["abs_sum"] / abs(want), "tol": 1e-10,
+            "ok": bool(max(rel_u, rel_us, rel_ud) <= 1e-10)}
 
     # a10: perm + dperm/dA of one 24x24 matrix (complex and real)
     for name, key, mat in (("a10_grad24c", "grad24c", workloads.haar_block(120, 24, workloads.SEED_HAAR120)),
