@@ -127,12 +127,15 @@ size_t perm_noalloc_scratch_bytes(void);
 #define PERM_ACC_PLAIN  1  /* plain double lane partial ("DD") */
 #define PERM_ACC_KAHAN  2  /* Kahan-compensated lane partial ("Kahan") */
 /* Extended precision, beyond the paper's modes: x, every product and the lane
- * partial in double-double (two-sum updates of x, FMA products), about 2^-104
- * per operation instead of 2^-53 and about eight times the work.  For deep
- * cancellation, where R(A) / |perm(A)| is large (about 1e6 for U[0,1) entries
- * at n = 40).  Orders 13..48 (PERM_EUNSUPPORTED otherwise; n = 0 gives 1);
- * log2_lanes, log2_reseed and the split launches apply as in the other
- * modes.  The staged copies and the workspace are those of the other modes. */
+ * partial in double-double, about 2^-104 per operation instead of 2^-53, and
+ * about three times the time of the FP64 walk.  The entries are split
+ * error-free on a power-of-two grid so that the high part of x is exact;
+ * every product is formed by FMA.  For deep cancellation, where
+ * R(A) / |perm(A)| is large (about 1e6 for U[0,1) entries at n = 40).  Orders
+ * 13..48 (PERM_EUNSUPPORTED otherwise; n = 0 gives 1).  log2_lanes,
+ * log2_reseed and the split launches apply as in the other modes.  The
+ * workspace is the one perm_workspace_bytes gives for the order, which holds
+ * the split entries for the orders this mode supports. */
 #define PERM_ACC_EXTENDED 3
 
 typedef struct {

@@ -72,6 +72,10 @@ DenseWs dense_ws_layout(int n, int components, int64_t blocks)
     off += align256(size_t(n) * size_t(components) * sizeof(double));
     L.partials = off;
     off += align256(size_t(std::max<int64_t>(blocks, 1)) * size_t(components) * sizeof(dd));
+    if (n <= (components == 1 ? kExtMaxN : kExtMaxNComplex)) {
+        L.ext = off;
+        off += align256(4 * nn);
+    }
     L.total = off;
     return L;
 }

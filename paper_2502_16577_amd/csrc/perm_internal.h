@@ -126,6 +126,8 @@ struct DenseWs {
     size_t aneg = 0;      // n*n scalars, its negation
     size_t x0 = 0;        // n scalars, Nijenhuis-Wilf start vector
     size_t partials = 0;  // one dd (per component) per block
+    size_t ext = 0;       // 4 n*n scalars for the extended walk's split entries
+                          // and their negations (orders it supports only)
     size_t total = 0;
 };
 

@@ -250,41 +250,60 @@ using DenseC128Table =
 
 // ---------------------------------------------------------------------------
 // Extended-precision complex walk (accumulation mode kAccExtended): the real
-// and imaginary parts of every x_i are double-doubles updated by two-sum,
+// and imaginary parts of every x_i are pairs exact in their high parts (the
+// entries are split error-free, below),
 // every factor of the product a complex double-double product (each real
 // product the rounded product of the high parts plus, as the low part, its
 // FMA rounding error and the cross terms; the two real sums by two-sum), and
 // the lane partial a complex double-double.  Each operation is then exact to
 // about 2^-104 of its operands.  One step per loop iteration; the lane
-// partitioning and re-seeds are those of the FP64 walk.  x0's low parts are
-// staged in the negated-column region, which this mode does not read.
+// partitioning and re-seeds are those of the FP64 walk.
 
+// Error-free split of the entries (both components) for the extended walk:
+// a = ah + al with ah a multiple of a power of two q and |al| <= q / 2, q
+// chosen from m = max_i sum_j (|re a_ij| + |im a_ij|) so that m / q < 2^50;
+// then every high part of x (a sum of multiples of q / 2 below 2^51 of them)
+// is exact in FP64 with one addition per flip.  `split` holds four arrays of
+// n x n interleaved (re, im) pairs, column-major like the column copies: ah,
+// al, -ah, -al (a flip adds the pair of the sign it needs).
 __global__ __launch_bounds__(kBlock) void prep_dense_c128_ext(int n, const perm_c128 *__restrict__ A,
-                                                              int64_t lda, double *__restrict__ acol,
-                                                              double *__restrict__ x0h,
-                                                              double *__restrict__ x0l)
+                                                              int64_t lda, double *__restrict__ split)
 {
+    __shared__ double rowabs[kBlock];
+    __shared__ double grid;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        double r = 0.0;
+        for (int j = 0; j < n; ++j) {
+            const perm_c128 v = A[int64_t(i) * lda + j];
+            r += __builtin_fabs(v.re) + __builtin_fabs(v.im);
+        }
+        rowabs[i] = r;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = 0.0;
+        for (int i = 0; i < n; ++i) m = rowabs[i] > m ? rowabs[i] : m;
+        int e = 0;
+        frexp(m > 0.0 ? m : 1.0, &e);  // m < 2^e
+        grid = ldexp(1.0, e - 50);
+    }
+    __syncthreads();
+    const double q = grid;
     for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
         const int j = idx / n;
         const int i = idx - j * n;
         const perm_c128 v = A[int64_t(i) * lda + j];
-        acol[2 * idx] = v.re;
-        acol[2 * idx + 1] = v.im;
-    }
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        double sr = 0.0, er = 0.0, si = 0.0, ei = 0.0;  // compensated row sums
-        for (int j = 0; j < n; ++j) {
-            const perm_c128 v = A[int64_t(i) * lda + j];
-            acc_add(sr, er, v.re);
-            acc_add(si, ei, v.im);
-        }
-        // x0_i = a_{i,n-1} - r_i / 2 as a double-double per component
-        const perm_c128 last = A[int64_t(i) * lda + n - 1];
-        double h, l;
-        two_sum(last.re, -0.5 * sr, h, l);
-        two_sum(h, l - 0.5 * er, x0h[2 * i], x0l[2 * i]);
-        two_sum(last.im, -0.5 * si, h, l);
-        two_sum(h, l - 0.5 * ei, x0h[2 * i + 1], x0l[2 * i + 1]);
+        const double hr = rint(v.re / q) * q, hi = rint(v.im / q) * q;  // exact
+        const double lr = v.re - hr, li = v.im - hi;  // exact: the bits below q
+        const int64_t nn2 = 2 * int64_t(n) * n;
+        split[2 * idx] = hr;
+        split[2 * idx + 1] = hi;
+        split[nn2 + 2 * idx] = lr;
+        split[nn2 + 2 * idx + 1] = li;
+        split[2 * nn2 + 2 * idx] = -hr;
+        split[2 * nn2 + 2 * idx + 1] = -hi;
+        split[3 * nn2 + 2 * idx] = -lr;
+        split[3 * nn2 + 2 * idx + 1] = -li;
     }
 }
 
@@ -330,28 +349,42 @@ __device__ __forceinline__ void cext_mul(double &arh, double &arl, double &aih, 
     ail = t + (p3l + p4l);
 }
 
-// x_i += v a_ij for both components (v = +1 or -1, or 0 in a re-seed).
+// x_i += f a_ij for both components of the split column (f = +-1/2 in a
+// re-seed): exact in the high parts, one rounded addition in each low part.
 template <int N>
 __device__ __forceinline__ void cext_add_column(double (&xrh)[N], double (&xrl)[N],
                                                 double (&xih)[N], double (&xil)[N],
-                                                const double *__restrict__ a, double v)
+                                                const double *__restrict__ ah,
+                                                const double *__restrict__ al, double f)
 {
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-        double s, t;
-        two_sum(xrh[i], v * a[2 * i], s, t);
-        xrh[i] = s;
-        xrl[i] += t;
-        two_sum(xih[i], v * a[2 * i + 1], s, t);
-        xih[i] = s;
-        xil[i] += t;
+        xrh[i] = __builtin_fma(f, ah[2 * i], xrh[i]);
+        xrl[i] = __builtin_fma(f, al[2 * i], xrl[i]);
+        xih[i] = __builtin_fma(f, ah[2 * i + 1], xih[i]);
+        xil[i] = __builtin_fma(f, al[2 * i + 1], xil[i]);
+    }
+}
+
+// A flip, x_i +-= a_ij, from the split pair of the flip's sign (high and low
+// parts 2 N * N apart): one add per part, with the column entry read from
+// scalar registers as its only scalar operand.
+template <int N>
+__device__ __forceinline__ void cext_flip_column(double (&xrh)[N], double (&xrl)[N],
+                                                 double (&xih)[N], double (&xil)[N],
+                                                 const double *__restrict__ col)
+{
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        xrh[i] += col[2 * i];
+        xrl[i] += col[2 * N * N + 2 * i];
+        xih[i] += col[2 * i + 1];
+        xil[i] += col[2 * N * N + 2 * i + 1];
     }
 }
 
 template <int N>
-__global__ __launch_bounds__(kBlock) void sweep_dense_c128_ext(const double *__restrict__ acol,
-                                                               const double *__restrict__ x0h,
-                                                               const double *__restrict__ x0l,
+__global__ __launch_bounds__(kBlock) void sweep_dense_c128_ext(const double *__restrict__ split,
                                                                dd *__restrict__ partials, int c,
                                                                int r, uint32_t l_begin,
                                                                uint32_t l_end, int accumulate)
@@ -365,31 +398,31 @@ __global__ __launch_bounds__(kBlock) void sweep_dense_c128_ext(const double *__r
     const uint64_t hbits = (g0 ^ (g0 >> 1)) >> c;
     const uint32_t rmask = (1u << r) - 1u;
 
+    const double *__restrict__ ahi = split;
+    const double *__restrict__ alo = split + 2 * N * N;
     double xrh[N], xrl[N], xih[N], xil[N];
     double srh = 0.0, srl = 0.0, sih = 0.0, sil = 0.0;  // lane partial
     for (uint32_t l = l_begin; l < l_end; ++l) {
         if ((l & rmask) == 0) {
+            // x = (a_{n-1} + sum_{j<n-1} s_j a_j) / 2, s_j = +1 for the columns
+            // in this step's Gray code, else -1
+            const uint32_t low = gray_low(l, kb, c);
 #pragma unroll
             for (int i = 0; i < N; ++i) {
-                xrh[i] = x0h[2 * i];
-                xrl[i] = x0l[2 * i];
-                xih[i] = x0h[2 * i + 1];
-                xil[i] = x0l[2 * i + 1];
+                xrh[i] = 0.5 * ahi[2 * ((N - 1) * N + i)];
+                xrl[i] = 0.5 * alo[2 * ((N - 1) * N + i)];
+                xih[i] = 0.5 * ahi[2 * ((N - 1) * N + i) + 1];
+                xil[i] = 0.5 * alo[2 * ((N - 1) * N + i) + 1];
             }
-            for (int j = c; j < N - 1; ++j) {
-                const double f = ((hbits >> (j - c)) & 1u) ? 1.0 : 0.0;
-                cext_add_column<N>(xrh, xrl, xih, xil, acol + 2 * j * N, f);
-            }
-            uint32_t low = gray_low(l, kb, c);
-            while (low) {
-                const int j = __builtin_ctz(low);
-                low &= low - 1u;
-                cext_add_column<N>(xrh, xrl, xih, xil, acol + 2 * j * N, 1.0);
+            for (int j = 0; j < N - 1; ++j) {
+                const bool in = j < c ? ((low >> j) & 1u) != 0u : ((hbits >> (j - c)) & 1u) != 0u;
+                cext_add_column<N>(xrh, xrl, xih, xil, ahi + 2 * j * N, alo + 2 * j * N,
+                                   in ? 0.5 : -0.5);
             }
         } else {
             const int j = __builtin_ctz(l);
             const bool add = (gray_low(l, kb, c) >> j) & 1u;
-            cext_add_column<N>(xrh, xrl, xih, xil, acol + 2 * j * N, add ? 1.0 : -1.0);
+            cext_flip_column<N>(xrh, xrl, xih, xil, split + (add ? 0 : 4 * N * N) + 2 * j * N);
         }
         // the product as two interleaved chains
         double prh[2], prl[2], pih[2], pil[2];
@@ -427,9 +460,8 @@ __global__ __launch_bounds__(kBlock) void sweep_dense_c128_ext(const double *__r
 }
 
 template <int N>
-static void launch_csweep_ext_n(const SweepPlan &p, int log2_reseed, const double *acol,
-                                const double *x0h, const double *x0l, dd *partials,
-                                hipStream_t stream)
+static void launch_csweep_ext_n(const SweepPlan &p, int log2_reseed, const double *split,
+                                dd *partials, hipStream_t stream)
 {
     // launches of at most 2^37 subset-steps (the walk is about 8 times slower
     // than the FP64 one), each over a consecutive range of every lane's chunk
@@ -441,12 +473,11 @@ static void launch_csweep_ext_n(const SweepPlan &p, int log2_reseed, const doubl
     span = std::min(pow2, C);
     for (int64_t l0 = 0; l0 < C; l0 += span)
         hipLaunchKernelGGL(sweep_dense_c128_ext<N>, dim3(unsigned(p.blocks)), dim3(kBlock), 0,
-                           stream, acol, x0h, x0l, partials, p.log2_chunk, log2_reseed,
-                           uint32_t(l0), uint32_t(l0 + span), int(l0 > 0));
+                           stream, split, partials, p.log2_chunk, log2_reseed, uint32_t(l0),
+                           uint32_t(l0 + span), int(l0 > 0));
 }
 
-using CExtLauncher = void (*)(const SweepPlan &, int, const double *, const double *,
-                              const double *, dd *, hipStream_t);
+using CExtLauncher = void (*)(const SweepPlan &, int, const double *, dd *, hipStream_t);
 
 template <int... Ns>
 struct CExtTable {
@@ -477,13 +508,10 @@ int launch_dense_c128_ext(int n, const perm_c128 *A, int64_t lda, perm_c128 *out
     int r = log2_reseed > 0 ? log2_reseed : p.log2_reseed;
     if (r > p.log2_chunk) r = p.log2_chunk;
     const DenseWs L = dense_ws_layout(n, 2, dense_ws_blocks(n));
-    double *acol = reinterpret_cast<double *>(ws + L.acol);
-    double *x0l = reinterpret_cast<double *>(ws + L.aneg);
-    double *x0h = reinterpret_cast<double *>(ws + L.x0);
+    double *split = reinterpret_cast<double *>(ws + L.ext);
     dd *partials = reinterpret_cast<dd *>(ws + L.partials);
-    hipLaunchKernelGGL(prep_dense_c128_ext, dim3(1), dim3(kBlock), 0, stream, n, A, lda, acol, x0h,
-                       x0l);
-    f(p, r, acol, x0h, x0l, partials, stream);
+    hipLaunchKernelGGL(prep_dense_c128_ext, dim3(1), dim3(kBlock), 0, stream, n, A, lda, split);
+    f(p, r, split, partials, stream);
     hipLaunchKernelGGL(finalize_partials, dim3(1), dim3(kBlock), 0, stream, partials, p.blocks, 2,
                        (n & 1) ? 2.0 : -2.0, reinterpret_cast<double *>(out));
     return hipGetLastError() == hipSuccess ? PERM_OK : PERM_EHIP;

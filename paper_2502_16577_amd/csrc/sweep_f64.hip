@@ -182,31 +182,51 @@ int64_t dense_launch_span(int n, const SweepPlan &p, const SweepOptions &o);
 // cancels deeply (R(A) / |perm(A)| about 1e6 for U[0,1) entries at n = 40)
 // those roundings, which are correlated along the Gray walk, leave a
 // relative error near 1e-10 even when x is rebuilt exactly every 16 steps.
-// Here every x_i is a double-double (hi, lo) updated by two-sum, every
-// product a double-double formed with FMA, and the lane partial a
-// double-double, so each operation is exact to about 2^-104 of its
-// operands.  About six times the FP64 walk's time; one step per loop
-// iteration; the lane partitioning, re-seeds and split launches are
-// those of the FP64 walk.  x0's low parts are staged in the negated-column
-// region, which this mode does not read.
+// Here every x_i is a pair (hi, lo) kept exactly in its high part (the
+// entries are split error-free, below), every product a double-double formed
+// with FMA, and the lane partial a double-double, so each operation is exact
+// to about 2^-104 of its operands.  One step per loop iteration; the lane
+// partitioning, re-seeds and split launches are those of the FP64 walk.
 
+// Error-free split of the entries for the extended walk: a = ah + al with
+// ah a multiple of a power of two q and |al| <= q / 2, q chosen from the
+// largest row sum m = max_i sum_j |a_ij| so that m / q < 2^50.  Every x_i of
+// the walk is (a_{i,n-1} + sum_{j<n-1} s_j a_ij) / 2 with s_j = +-1, so its
+// high part, a sum of multiples of q / 2 below 2^51 of them, is exact in FP64
+// with one addition per flip, and the low parts are small enough that FP64
+// sums of them are accurate to about 2^-104 of m.  `split` holds four n x n
+// column-major arrays: ah, al, -ah, -al (a flip adds the pair of the sign it
+// needs, as the FP64 walk picks between its column and its negation).
 __global__ __launch_bounds__(kBlock) void prep_dense_ext(int n, const double *__restrict__ A,
-                                                         int64_t lda, double *__restrict__ acol,
-                                                         double *__restrict__ x0h,
-                                                         double *__restrict__ x0l)
+                                                         int64_t lda, double *__restrict__ split)
 {
+    __shared__ double rowabs[kBlock];
+    __shared__ double grid;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        double r = 0.0;
+        for (int j = 0; j < n; ++j) r += __builtin_fabs(A[int64_t(i) * lda + j]);
+        rowabs[i] = r;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = 0.0;
+        for (int i = 0; i < n; ++i) m = rowabs[i] > m ? rowabs[i] : m;
+        int e = 0;
+        frexp(m > 0.0 ? m : 1.0, &e);  // m < 2^e (a rounded row sum is within 2^-45 of its value)
+        grid = ldexp(1.0, e - 50);
+    }
+    __syncthreads();
+    const double q = grid;
     for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
         const int j = idx / n;
         const int i = idx - j * n;
-        acol[idx] = A[int64_t(i) * lda + j];
-    }
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        double s = 0.0, e = 0.0;  // compensated row sum r_i = s + e
-        for (int j = 0; j < n; ++j) acc_add(s, e, A[int64_t(i) * lda + j]);
-        // x0_i = a_{i,n-1} - r_i / 2 as a double-double (halving is exact)
-        double h, l;
-        two_sum(A[int64_t(i) * lda + n - 1], -0.5 * s, h, l);
-        two_sum(h, l - 0.5 * e, x0h[i], x0l[i]);
+        const double a = A[int64_t(i) * lda + j];
+        const double h = rint(a / q) * q;  // exact: q is a power of two
+        const double l = a - h;            // exact: the bits of a below q
+        split[idx] = h;
+        split[n * n + idx] = l;
+        split[2 * n * n + idx] = -h;
+        split[3 * n * n + idx] = -l;
     }
 }
 
@@ -229,41 +249,51 @@ __device__ __forceinline__ void ext_mul(double &ah, double &al, double bh, doubl
     al = e;
 }
 
-// x_i += v a_ij (v = +1 or -1): the rounding error of the high part goes to
-// the low part.
+// x_i += f a_ij for the split column (f = +-1/2 in a re-seed):
+// exact in the high part, one rounded addition in the low part.
 template <int N>
 __device__ __forceinline__ void ext_add_column(double (&xh)[N], double (&xl)[N],
-                                               const double *__restrict__ a, double v)
+                                               const double *__restrict__ ah,
+                                               const double *__restrict__ al, double f)
 {
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-        double s, t;
-        two_sum(xh[i], v * a[i], s, t);
-        xh[i] = s;
-        xl[i] += t;
+        xh[i] = __builtin_fma(f, ah[i], xh[i]);
+        xl[i] = __builtin_fma(f, al[i], xl[i]);
     }
 }
 
+// A flip, x_i +-= a_ij, from the split pair of the flip's sign (ah and al,
+// or their negations, at a distance of N * N): one add per part, with the
+// column entry read from scalar registers as its only scalar operand.
 template <int N>
-__device__ __forceinline__ void ext_reseed(double (&xh)[N], double (&xl)[N],
-                                           const double *__restrict__ acol,
-                                           const double *__restrict__ x0h,
-                                           const double *__restrict__ x0l, uint64_t hbits,
-                                           uint32_t low, int c)
+__device__ __forceinline__ void ext_flip_column(double (&xh)[N], double (&xl)[N],
+                                                const double *__restrict__ col)
 {
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-        xh[i] = x0h[i];
-        xl[i] = x0l[i];
+        xh[i] += col[i];
+        xl[i] += col[N * N + i];
     }
-    for (int j = c; j < N - 1; ++j) {
-        const double f = ((hbits >> (j - c)) & 1u) ? 1.0 : 0.0;
-        ext_add_column<N>(xh, xl, acol + j * N, f);  // adds 0 for columns not in the set
+}
+
+// x = (a_{n-1} + sum_{j<n-1} s_j a_j) / 2 with s_j = +1 for the columns in the
+// Gray code of this lane's step (bits below c wave-uniform in `low`, the
+// others the lane's `hbits`), else -1.
+template <int N>
+__device__ __forceinline__ void ext_reseed(double (&xh)[N], double (&xl)[N],
+                                           const double *__restrict__ ahi, uint64_t hbits,
+                                           uint32_t low, int c)
+{
+    const double *__restrict__ alo = ahi + N * N;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        xh[i] = 0.5 * ahi[(N - 1) * N + i];
+        xl[i] = 0.5 * alo[(N - 1) * N + i];
     }
-    while (low) {
-        const int j = __builtin_ctz(low);
-        low &= low - 1u;
-        ext_add_column<N>(xh, xl, acol + j * N, 1.0);
+    for (int j = 0; j < N - 1; ++j) {
+        const bool in = j < c ? ((low >> j) & 1u) != 0u : ((hbits >> (j - c)) & 1u) != 0u;
+        ext_add_column<N>(xh, xl, ahi + j * N, alo + j * N, in ? 0.5 : -0.5);
     }
 }
 
@@ -289,9 +319,7 @@ __device__ __forceinline__ void ext_product(const double (&xh)[N], const double 
 }
 
 template <int N>
-__global__ __launch_bounds__(kBlock) void sweep_dense_ext(const double *__restrict__ acol,
-                                                          const double *__restrict__ x0h,
-                                                          const double *__restrict__ x0l,
+__global__ __launch_bounds__(kBlock) void sweep_dense_ext(const double *__restrict__ split,
                                                           dd *__restrict__ partials, int c, int r,
                                                           uint32_t l_begin, uint32_t l_end,
                                                           int accumulate)
@@ -309,11 +337,11 @@ __global__ __launch_bounds__(kBlock) void sweep_dense_ext(const double *__restri
     double sh = 0.0, sl = 0.0;  // lane partial, double-double
     for (uint32_t l = l_begin; l < l_end; ++l) {
         if ((l & rmask) == 0) {
-            ext_reseed<N>(xh, xl, acol, x0h, x0l, hbits, gray_low(l, kb, c), c);
+            ext_reseed<N>(xh, xl, split, hbits, gray_low(l, kb, c), c);
         } else {
             const int j = __builtin_ctz(l);
             const bool add = (gray_low(l, kb, c) >> j) & 1u;
-            ext_add_column<N>(xh, xl, acol + j * N, add ? 1.0 : -1.0);
+            ext_flip_column<N>(xh, xl, split + (add ? 0 : 2 * N * N) + j * N);
         }
         double ph, pl;
         ext_product<N>(xh, xl, ph, pl);
@@ -331,8 +359,8 @@ __global__ __launch_bounds__(kBlock) void sweep_dense_ext(const double *__restri
 }
 
 template <int N>
-static void launch_ext_n(const SweepPlan &p, const SweepOptions &o, const double *acol,
-                         const double *x0h, const double *x0l, dd *partials, hipStream_t stream)
+static void launch_ext_n(const SweepPlan &p, const SweepOptions &o, const double *split,
+                         dd *partials, hipStream_t stream)
 {
     const int64_t C = int64_t(1) << p.log2_chunk;
     const int64_t span = dense_launch_span(N, p, o);
@@ -342,13 +370,13 @@ static void launch_ext_n(const SweepPlan &p, const SweepOptions &o, const double
     for (int64_t i = first; i < end; ++i) {
         const int64_t l0 = i * span;
         hipLaunchKernelGGL((sweep_dense_ext<N>), dim3(unsigned(p.blocks)), dim3(kBlock), 0, stream,
-                           acol, x0h, x0l, partials, p.log2_chunk, o.log2_reseed, uint32_t(l0),
+                           split, partials, p.log2_chunk, o.log2_reseed, uint32_t(l0),
                            uint32_t(l0 + span), int(l0 > 0));
     }
 }
 
-using ExtLauncher = void (*)(const SweepPlan &, const SweepOptions &, const double *,
-                             const double *, const double *, dd *, hipStream_t);
+using ExtLauncher = void (*)(const SweepPlan &, const SweepOptions &, const double *, dd *,
+                             hipStream_t);
 
 template <int... Ns>
 struct ExtTable {
@@ -490,11 +518,11 @@ int launch_dense_f64_opt(int n, const double *A, int64_t lda, double *out, const
         if (n < kExtMinN || n > kExtMaxN || p.log2_chunk < 1) return PERM_EUNSUPPORTED;
         ExtLauncher f = DenseExtTable::get(n);
         if (!f) return PERM_EUNSUPPORTED;
-        hipLaunchKernelGGL(prep_dense_ext, dim3(1), dim3(kBlock), 0, stream, n, A, lda, acol, x0,
-                           aneg);
+        double *split = reinterpret_cast<double *>(ws + L.ext);
+        hipLaunchKernelGGL(prep_dense_ext, dim3(1), dim3(kBlock), 0, stream, n, A, lda, split);
         SweepOptions oo = o;
         if (oo.log2_reseed < 1 || oo.log2_reseed > p.log2_chunk) oo.log2_reseed = p.log2_chunk;
-        f(p, oo, acol, x0, aneg, partials, stream);
+        f(p, oo, split, partials, stream);
         hipLaunchKernelGGL(finalize_partials, dim3(1), dim3(kBlock), 0, stream, partials, p.blocks,
                            1, (n & 1) ? 2.0 : -2.0, out);
         return hipGetLastError() == hipSuccess ? PERM_OK : PERM_EHIP;
