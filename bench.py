@@ -339,6 +339,14 @@ def measure_rows():
         "issue_slot_utilisation": ops / (ms * 1e-3) / LANE_OPS_PER_S,
         "abs_err": err, "tol": min(1e-13 * g["abs_sum"], 1e-10 * g["abs_perm"]),
         "ok": bool(err <= 1e-13 * g["abs_sum"] and err <= 1e-10 * g["abs_perm"])}
+    # the same matrix in the extended-precision walk (double-double x,
+    # products and lane sums), against the same stored value
+    api.perm_dense_c128_ex(A, accumulation=api.ACC_EXTENDED, out=out, ws=ws)
+    ms_ext = _timed(lambda: api.perm_dense_c128_ex(A, accumulation=api.ACC_EXTENDED, out=out,
+                                                   ws=ws), 3, st)
+    err_ext = abs(complex(out.item()) - want)
+    rows["a7_complex30"].update({"extended_ms": ms_ext, "extended_abs_err": err_ext,
+                                 "extended_ok": bool(err_ext <= 1e-10 * g["abs_perm"])})
 
     # a9: exact binary, 32x32 Bernoulli and the 40x40 sparse pattern
     for name, key, a01 in (("a9_binary32", "bernoulli32", workloads.bernoulli(32, workloads.SEED_BERNOULLI32)),
