@@ -334,13 +334,16 @@ def test_options_at_small_orders(oracle, n):
     assert abs(v - want) <= 1e-10 * abs(want)
 
 
-def test_split_sweep_over_several_calls(oracle):
+@pytest.mark.parametrize("acc", ["twosum", "extended"])
+def test_split_sweep_over_several_calls(oracle, acc):
     # the 8 launches of a split sweep run by one call, by eight calls of one
     # launch and by three calls of 3 + 3 + 2 launches (same workspace): the
-    # same value bit for bit, and the oracle's value within tolerance
+    # same value bit for bit, and the oracle's value within tolerance (the
+    # extended walk: within its double-double scale of the Ryser sum)
     a = W.uniform(26, 77)
     A = torch.from_numpy(a).to(DEV)
-    opts = dict(log2_reseed=4, max_steps_per_launch=1 << 22)
+    mode = api.ACC_EXTENDED if acc == "extended" else api.ACC_TWOSUM
+    opts = dict(accumulation=mode, log2_reseed=4, max_steps_per_launch=1 << 22)
     nl = api.dense_f64_launches(26, **opts)
     assert nl == 8
     ws = torch.empty(api.workspace_bytes(1, 26), dtype=torch.uint8, device=DEV)
@@ -350,8 +353,11 @@ def test_split_sweep_over_several_calls(oracle):
         for first, count in ranges:
             api.perm_dense_f64_ex(A, first_launch=first, launch_count=count, out=out, ws=ws, **opts)
         assert out.item() == one, ranges
-    want = oracle.ryser(a)
-    assert abs(one - want) <= 1e-10 * abs(want)
+    want, r = oracle.ryser(a, with_abs=True)
+    if acc == "extended":
+        assert abs(one - want) <= 1e-15 * r + 2.0 ** -52 * abs(want), (one, want, r)
+    else:
+        assert abs(one - want) <= 1e-10 * abs(want)
 
 
 def _exact_perm_gaussian(m):
