@@ -52,8 +52,8 @@ GOLDEN = os.path.join(ROOT, "tests", "golden")
 # plain 1 GiB copy (profiles/sweep_dense_f64_n32_u01.md).  Valid only for the
 # kernel source they were measured on; reported as null once it changes.
 COUNTERS_SRC = os.path.join(ROOT, "paper_2502_16577_amd", "csrc", "sweep_f64.hip")
-COUNTERS_SRC_SHA256 = "77b9c4f8ba1d4c9f8fd241e7cfff611ddc1bbab3c361272ba30cfea8f2723351"
-TRAFFIC_BYTES_PER_LAUNCH = 187.5 * 1024 * 2.000 + 32 * 1024 * 1.000
+COUNTERS_SRC_SHA256 = "403a22227bc7a5e8ce6c85ab6d5fabf4e256fb0d14ca2f8fe50671f0261332a8"
+TRAFFIC_BYTES_PER_LAUNCH = 182.5 * 1024 * 2.000 + 32 * 1024 * 1.000
 
 
 def traffic_bytes():

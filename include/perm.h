@@ -129,7 +129,7 @@ size_t perm_noalloc_scratch_bytes(void);
 /* Extended precision, beyond the paper's modes: x, every product and the lane
  * partial in double-double, about 2^-104 per operation instead of 2^-53, and
  * about three times the time of the FP64 walk.  The entries are split
- * error-free on a power-of-two grid so that the high part of x is exact;
+ * error-free on a power-of-two grid per row so that the high part of x is exact;
  * every product is formed by FMA.  For deep cancellation, where
  * R(A) / |perm(A)| is large (about 1e6 for U[0,1) entries at n = 40).  Orders
  * 13..48 (PERM_EUNSUPPORTED otherwise; n = 0 gives 1).  log2_lanes,

@@ -259,39 +259,36 @@ using DenseC128Table =
 // about 2^-104 of its operands.  One step per loop iteration; the lane
 // partitioning and re-seeds are those of the FP64 walk.
 
-// Error-free split of the entries (both components) for the extended walk:
-// a = ah + al with ah a multiple of a power of two q and |al| <= q / 2, q
-// chosen from m = max_i sum_j (|re a_ij| + |im a_ij|) so that m / q < 2^50;
-// then every high part of x (a sum of multiples of q / 2 below 2^51 of them)
-// is exact in FP64 with one addition per flip.  `split` holds four arrays of
-// n x n interleaved (re, im) pairs, column-major like the column copies: ah,
-// al, -ah, -al (a flip adds the pair of the sign it needs).
+// Error-free split of the entries (both components) for the extended walk,
+// row by row: a_ij = ah_ij + al_ij with ah_ij a multiple of a power of two q_i
+// and |al_ij| <= q_i / 2 in each component, q_i chosen from the row's sum
+// m_i = sum_j (|re a_ij| + |im a_ij|) so that m_i / q_i < 2^50; then both high
+// parts of x_i (sums of multiples of q_i / 2 below 2^51 of them) are exact in
+// FP64 with one addition per flip.  The grid is per row as in the real walk:
+// a shared grid would leave rows of much smaller scale in their low parts,
+// whose products with each other the double-double product does not keep.
+// `split` holds four arrays of n x n interleaved (re, im) pairs,
+// column-major like the column copies: ah, al, -ah, -al (a flip adds the pair
+// of the sign it needs).
 __global__ __launch_bounds__(kBlock) void prep_dense_c128_ext(int n, const perm_c128 *__restrict__ A,
                                                               int64_t lda, double *__restrict__ split)
 {
-    __shared__ double rowabs[kBlock];
-    __shared__ double grid;
+    __shared__ double grid[kBlock];
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        double r = 0.0;
+        double m = 0.0;
         for (int j = 0; j < n; ++j) {
             const perm_c128 v = A[int64_t(i) * lda + j];
-            r += __builtin_fabs(v.re) + __builtin_fabs(v.im);
+            m += __builtin_fabs(v.re) + __builtin_fabs(v.im);
         }
-        rowabs[i] = r;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double m = 0.0;
-        for (int i = 0; i < n; ++i) m = rowabs[i] > m ? rowabs[i] : m;
         int e = 0;
         frexp(m > 0.0 ? m : 1.0, &e);  // m < 2^e
-        grid = ldexp(1.0, e - 50);
+        grid[i] = ldexp(1.0, e - 50 > -1074 ? e - 50 : -1074);  // no grid below the least double
     }
     __syncthreads();
-    const double q = grid;
     for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
         const int j = idx / n;
         const int i = idx - j * n;
+        const double q = grid[i];
         const perm_c128 v = A[int64_t(i) * lda + j];
         const double hr = rint(v.re / q) * q, hi = rint(v.im / q) * q;  // exact
         const double lr = v.re - hr, li = v.im - hi;  // exact: the bits below q

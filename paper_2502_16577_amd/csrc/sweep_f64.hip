@@ -188,38 +188,35 @@ int64_t dense_launch_span(int n, const SweepPlan &p, const SweepOptions &o);
 // to about 2^-104 of its operands.  One step per loop iteration; the lane
 // partitioning, re-seeds and split launches are those of the FP64 walk.
 
-// Error-free split of the entries for the extended walk: a = ah + al with
-// ah a multiple of a power of two q and |al| <= q / 2, q chosen from the
-// largest row sum m = max_i sum_j |a_ij| so that m / q < 2^50.  Every x_i of
-// the walk is (a_{i,n-1} + sum_{j<n-1} s_j a_ij) / 2 with s_j = +-1, so its
-// high part, a sum of multiples of q / 2 below 2^51 of them, is exact in FP64
-// with one addition per flip, and the low parts are small enough that FP64
-// sums of them are accurate to about 2^-104 of m.  `split` holds four n x n
-// column-major arrays: ah, al, -ah, -al (a flip adds the pair of the sign it
-// needs, as the FP64 walk picks between its column and its negation).
+// Error-free split of the entries for the extended walk, row by row: a_ij =
+// ah_ij + al_ij with ah_ij a multiple of a power of two q_i and |al_ij| <=
+// q_i / 2, q_i chosen from the row's absolute sum m_i = sum_j |a_ij| so that
+// m_i / q_i < 2^50.  Every x_i of the walk is (a_{i,n-1} + sum_{j<n-1} s_j
+// a_ij) / 2 with s_j = +-1, so its high part, a sum of multiples of q_i / 2
+// below 2^51 of them, is exact in FP64 with one addition per flip, and its
+// low part stays below n q_i / 4.  The grid is per row because each x_i uses
+// only its own row: a grid shared by rows of very different scale would put
+// a small row wholly in its low part, and the product, which keeps the cross
+// terms of high and low parts but not low times low, would lose every term
+// with two such rows.  `split` holds four n x n column-major arrays: ah, al,
+// -ah, -al (a flip adds the pair of the sign it needs, as the FP64 walk
+// picks between its column and its negation).
 __global__ __launch_bounds__(kBlock) void prep_dense_ext(int n, const double *__restrict__ A,
                                                          int64_t lda, double *__restrict__ split)
 {
-    __shared__ double rowabs[kBlock];
-    __shared__ double grid;
+    __shared__ double grid[kBlock];
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        double r = 0.0;
-        for (int j = 0; j < n; ++j) r += __builtin_fabs(A[int64_t(i) * lda + j]);
-        rowabs[i] = r;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
         double m = 0.0;
-        for (int i = 0; i < n; ++i) m = rowabs[i] > m ? rowabs[i] : m;
+        for (int j = 0; j < n; ++j) m += __builtin_fabs(A[int64_t(i) * lda + j]);
         int e = 0;
         frexp(m > 0.0 ? m : 1.0, &e);  // m < 2^e (a rounded row sum is within 2^-45 of its value)
-        grid = ldexp(1.0, e - 50);
+        grid[i] = ldexp(1.0, e - 50 > -1074 ? e - 50 : -1074);  // no grid below the least double
     }
     __syncthreads();
-    const double q = grid;
     for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
         const int j = idx / n;
         const int i = idx - j * n;
+        const double q = grid[i];
         const double a = A[int64_t(i) * lda + j];
         const double h = rint(a / q) * q;  // exact: q is a power of two
         const double l = a - h;            // exact: the bits of a below q

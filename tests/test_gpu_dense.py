@@ -441,3 +441,44 @@ def test_complex_extended_haar_vs_oracle(oracle, n):
     assert abs(got - want) <= 1e-13 * r, (n, got, want, r)
     d = complex(api.perm_dense_c128_ex(A).cpu().item())
     assert d == complex(api.perm_dense_c128(A).cpu().item())
+
+
+def _row_scales(n, offset):
+    """Powers of two 2^k_i with k = +-60, +-50, ... alternating, and k_0 raised by
+    `offset`: row scales spanning 2^120, with prod d = 2^offset."""
+    k = np.array([(60 - 10 * (i // 2 % 6)) * (1 if i % 2 == 0 else -1) for i in range(n)])
+    if n % 2:
+        k[-1] = 0  # the unpaired last exponent
+    k[0] += offset
+    assert k.sum() == offset
+    return np.ldexp(1.0, k)
+
+
+@pytest.mark.parametrize("n", [16, 23])
+def test_extended_rows_of_very_different_scale(oracle, n):
+    # perm(D B) = prod d perm(B) for D = diag(d), and scaling a row by a power
+    # of two commutes with every operation of the walk (the split grid is set
+    # per row), so the extended walk returns prod d times its value on B bit for
+    # bit.  A grid shared by all rows would put the 2^-60 rows wholly in their
+    # low parts, whose products with each other the walk does not keep.
+    b = 2.0 * W.uniform(n, 1700 + n) - 1.0
+    d = _row_scales(n, 7)
+    got_b = api.perm_dense_f64_ex(torch.from_numpy(b).to(DEV), accumulation=api.ACC_EXTENDED).item()
+    got_a = api.perm_dense_f64_ex(torch.from_numpy(d[:, None] * b).to(DEV),
+                                  accumulation=api.ACC_EXTENDED).item()
+    assert got_a == 2.0 ** 7 * got_b, (n, got_a, got_b)
+    want, r = oracle.ryser(b, with_abs=True)
+    assert abs(got_b - want) <= 1e-15 * r + 2.0 ** -52 * abs(want), (n, got_b, want, r)
+
+
+def test_complex_extended_rows_of_very_different_scale(oracle):
+    # the complex walk's split grid is per row too
+    n = 16
+    b = W.haar_block(2 * n, n, 1800 + n)
+    d = _row_scales(n, -5)
+    f = lambda m: complex(api.perm_dense_c128_ex(torch.from_numpy(np.ascontiguousarray(m)).to(DEV),
+                                                 accumulation=api.ACC_EXTENDED).cpu().item())
+    got_b, got_a = f(b), f(d[:, None] * b)
+    assert got_a == 2.0 ** -5 * got_b, (got_a, got_b)
+    want, r = oracle.ryser(b, with_abs=True)
+    assert abs(got_b - want) <= 1e-13 * r, (got_b, want, r)
