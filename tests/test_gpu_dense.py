@@ -18,6 +18,8 @@ import torch
 from paper_2502_16577_amd import api
 from paper_2502_16577_amd import workloads as W
 
+from closed_forms import all_ones_first_launch
+
 pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "full_size.json")
 DEV = torch.device("cuda:0")
@@ -484,28 +486,6 @@ def test_complex_extended_rows_of_very_different_scale(oracle):
     assert abs(got_b - want) <= 1e-13 * r, (got_b, want, r)
 
 
-def _all_ones_first_launch(n, log2_lanes, span):
-    """perm_dense_f64_ex's output after only the first launch of a split sweep
-    of the all-ones matrix: 2 (-1)^(n-1) times the sum over lanes K < 2^m
-    (m = log2_lanes) and steps l < span of (-1)^l x^n, x = pc + 1 - n/2 with pc
-    the number of columns j < n - 1 in the Gray code of g = K 2^c + l.  For
-    l < 2^(c-1), pc = popcount(Gray(K)) + (K & 1) + popcount(Gray(l)); bit 0 of
-    K is the parity of popcount(Gray(K)), and popcount(Gray(K)) = k for C(m, k)
-    of the K (Gray coding is a bijection).  Returns (value, sum of |terms|),
-    exact as Fractions."""
-    m = log2_lanes
-    tot = 0
-    absum = 0
-    for k in range(m + 1):
-        v = k + (k & 1)
-        for l in range(span):
-            y = 2 * (v + bin(l ^ (l >> 1)).count("1") + 1) - n  # y = 2x
-            t = math.comb(m, k) * y ** n
-            tot += -t if l & 1 else t
-            absum += abs(t)
-    scale = fractions.Fraction(2, 2 ** n)
-    return (scale * tot if n % 2 else -scale * tot), scale * absum
-
 
 @pytest.mark.parametrize("n,acc,log2_lanes", [(63, "twosum", 31), (48, "twosum", 18),
                                               (48, "extended", 18)])
@@ -521,7 +501,7 @@ def test_largest_orders_first_launch_closed_form(n, acc, log2_lanes):
     assert api.dense_f64_launches(n, **opts) == 1 << (c - 4)  # pins lanes = 2^log2_lanes
     A = torch.ones((n, n), dtype=torch.float64, device=DEV)
     got = api.perm_dense_f64_ex(A, first_launch=0, launch_count=1, **opts).item()
-    want, r = _all_ones_first_launch(n, log2_lanes, span)
+    want, r = all_ones_first_launch(n, log2_lanes, span)
     err = abs(fractions.Fraction(got) - want)
     if acc == "extended":
         assert err <= fractions.Fraction(2.0 ** -52) * abs(want) + fractions.Fraction(1, 10 ** 26) * r, (
