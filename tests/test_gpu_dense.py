@@ -414,7 +414,7 @@ def test_complex_extended_gaussian_integers(n):
     assert abs(got.real - er) <= gate and abs(got.imag - ei) <= gate, (n, got, er, ei, r / mod)
 
 
-@pytest.mark.parametrize("n", [24, 30])
+@pytest.mark.parametrize("n", [24, 30, 32])
 def test_complex_extended_all_equal(n):
     # every entry c: perm = n! c^n in exact rational arithmetic
     c = complex(0.6, 0.5)
@@ -508,3 +508,24 @@ def test_largest_orders_first_launch_closed_form(n, acc, log2_lanes):
             n, got, float(want))
     else:
         assert err <= fractions.Fraction(1, 10 ** 13) * r, (n, got, float(want), float(r))
+
+
+@pytest.mark.parametrize("n", [36, 40])
+def test_complex_all_equal_beyond_the_configs(n):
+    # the FP64 complex sweep above the 30 x 30 configuration: every entry c,
+    # perm = n! c^n exactly, gated at the forward-error scale n u R with R =
+    # |c|^n R(J_n), R(J_n) = 2 sum_k C(n-1, k) |k + 1 - n/2|^n in closed form
+    c = complex(0.6, 0.5)
+    cr, ci = fractions.Fraction(c.real), fractions.Fraction(c.imag)
+    pr, pi = fractions.Fraction(1), fractions.Fraction(0)
+    for _ in range(n):
+        pr, pi = pr * cr - pi * ci, pr * ci + pi * cr
+    f = math.factorial(n)
+    er, ei = f * pr, f * pi
+    rj = 2 * sum(math.comb(n - 1, k) * abs(fractions.Fraction(2 * (k + 1) - n, 2)) ** n
+                 for k in range(n))
+    r = rj * fractions.Fraction(abs(c)) ** n
+    got = complex(api.perm(torch.from_numpy(np.full((n, n), c)).to(DEV)).cpu().item())
+    gate = n * fractions.Fraction(2.0 ** -53) * r
+    assert abs(fractions.Fraction(got.real) - er) <= gate, (n, got, float(er), float(gate))
+    assert abs(fractions.Fraction(got.imag) - ei) <= gate, (n, got, float(ei), float(gate))
