@@ -52,8 +52,8 @@ GOLDEN = os.path.join(ROOT, "tests", "golden")
 # plain 1 GiB copy (profiles/sweep_dense_f64_n32_u01.md).  Valid only for the
 # kernel source they were measured on; reported as null once it changes.
 COUNTERS_SRC = os.path.join(ROOT, "paper_2502_16577_amd", "csrc", "sweep_f64.hip")
-COUNTERS_SRC_SHA256 = "403a22227bc7a5e8ce6c85ab6d5fabf4e256fb0d14ca2f8fe50671f0261332a8"
-TRAFFIC_BYTES_PER_LAUNCH = 182.5 * 1024 * 2.000 + 32 * 1024 * 1.000
+COUNTERS_SRC_SHA256 = "bb41e5ba510883f728a454befe2ef0f1682db634e86eec74dda9464e9ddee02a"
+TRAFFIC_BYTES_PER_LAUNCH = 188.0 * 1024 * 2.000 + 32 * 1024 * 1.000
 
 
 def traffic_bytes():

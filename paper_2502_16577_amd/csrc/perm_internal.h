@@ -224,6 +224,12 @@ int launch_dense_f64_opt(int n, const double *A, int64_t lda, double *out, const
 // The dense sweep's plan under the options, and the number of launches the
 // sweep is split into (1 for n <= 12).
 SweepPlan dense_plan(int n, const SweepOptions &o);
+// Steps of every lane's chunk per launch of the dense walks (a power of two,
+// a multiple of the re-seed interval).
+int64_t dense_launch_span(int n, const SweepPlan &p, const SweepOptions &o);
+// The extended-precision dense walk (sweep_ext.hip), n >= 1.
+int launch_dense_ext(int n, const double *A, int64_t lda, double *out, const SweepOptions &o,
+                     char *ws, hipStream_t stream);
 int64_t dense_f64_launches(int n, const SweepOptions &o);
 int launch_dense_c128_ext(int n, const perm_c128 *A, int64_t lda, perm_c128 *out,
                           int log2_reseed, char *ws, hipStream_t stream);
