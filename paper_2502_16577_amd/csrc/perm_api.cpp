@@ -116,6 +116,9 @@ GradWs grad_ws_layout(int n, int components, int64_t waves)
     L.grad_partials = off;
     off += align256(size_t(std::max<int64_t>(waves, 1)) * size_t(components) * size_t(n) *
                     size_t(n) * sizeof(dd));
+    L.grad_sums = off;
+    off += align256(size_t(grad_sum_slices(waves)) * size_t(components) * size_t(n) * size_t(n) *
+                    sizeof(dd));
     L.total = off;
     return L;
 }

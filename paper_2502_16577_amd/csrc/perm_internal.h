@@ -170,8 +170,17 @@ struct GradWs {
     size_t acol = 0, x0 = 0;            // staged columns (grad_rows(n) rows each), start vector
     size_t perm_partials = 0;           // waves * 2 dd
     size_t grad_partials = 0;           // waves * components * n * n dd
+    size_t grad_sums = 0;               // grad_sum_slices(waves) * components * n * n dd
     size_t total = 0;
 };
+
+// The items' G partials are summed in two fixed-order passes: over slices of
+// the items (about 16 items a slice, at most 64 slices), then over the slices.
+inline int grad_sum_slices(int64_t items)
+{
+    const int64_t s = items / 16;
+    return int(s < 1 ? 1 : s > 64 ? 64 : s);
+}
 
 GradWs grad_ws_layout(int n, int components, int64_t waves);
 // Waves per gradient work item; they split the matrix's rows (grad_item.h).

@@ -97,13 +97,42 @@ __global__ void grad_order1(const double *__restrict__ a, int cplx, double *__re
     }
 }
 
-// Sums the waves' shares in a fixed order: one block per entry (i, j, comp)
-// of G, threads striding over the waves; block 0 also sums the permanent.
-// Writes (-1)^(n-1) G and 2 (-1)^(n-1) sum.
+// First pass over the items' G partials, read coalesced: block (t, s) takes
+// the entries 64 t .. 64 t + 63 (one per lane) and the items of slice s, wave
+// w every fourth item from the slice's w-th, then adds its waves in order.
+template <int N, bool CPLX>
+__global__ __launch_bounds__(kBlock) void grad_slice_sums(const dd *__restrict__ g_part,
+                                                          int64_t items, int slices,
+                                                          dd *__restrict__ g_sum)
+{
+    constexpr int E = (CPLX ? 2 : 1) * N * N;
+    __shared__ dd red[kWavesPerBlock][kWave];
+    const int lane = int(threadIdx.x) & (kWave - 1);
+    const int w = int(threadIdx.x) / kWave;
+    const int e = int(blockIdx.x) * kWave + lane;
+    const int64_t per = (items + slices - 1) / slices;
+    const int64_t v0 = int64_t(blockIdx.y) * per;
+    const int64_t v1 = v0 + per < items ? v0 + per : items;
+    dd acc = dd{0.0, 0.0};
+    if (e < E)
+        for (int64_t v = v0 + w; v < v1; v += kWavesPerBlock) acc = dd_add(acc, g_part[v * E + e]);
+    red[w][lane] = acc;
+    __syncthreads();
+    if (w == 0 && e < E) {
+        dd t = red[0][lane];
+        for (int q = 1; q < kWavesPerBlock; ++q) t = dd_add(t, red[q][lane]);
+        g_sum[int64_t(blockIdx.y) * E + e] = t;
+    }
+}
+
+// Second pass: G = (-1)^(n-1) times the sum of the slices' sums, one wave per
+// entry (lane s reads slice s's sum; at most 64 slices) combined by a fixed
+// shuffle tree; block 0 also writes 2 (-1)^(n-1) times the sum of the items'
+// permanent shares.
 template <int N, bool CPLX>
 __global__ __launch_bounds__(kBlock) void finalize_grad(const dd *__restrict__ perm_part,
-                                                        const dd *__restrict__ g_part,
-                                                        int64_t waves,
+                                                        const dd *__restrict__ g_sum,
+                                                        int64_t items, int slices,
                                                         double *__restrict__ out_perm,
                                                         double *__restrict__ out_grad)
 {
@@ -111,15 +140,16 @@ __global__ __launch_bounds__(kBlock) void finalize_grad(const dd *__restrict__ p
     constexpr int E = W * N * N;
     __shared__ dd red[kWavesPerBlock];
     const double sgn = (N & 1) ? 1.0 : -1.0;
-    const int e = int(blockIdx.x);
-    dd acc = dd{0.0, 0.0};
-    for (int64_t v = threadIdx.x; v < waves; v += kBlock) acc = dd_add(acc, g_part[v * E + e]);
-    const dd t = block_reduce_dd(acc, red);
-    if (threadIdx.x == 0) out_grad[e] = sgn * (t.hi + t.lo);
+    const int lane = int(threadIdx.x) & (kWave - 1);
+    const int e = int(blockIdx.x) * kWavesPerBlock + int(threadIdx.x) / kWave;
+    dd t = dd{0.0, 0.0};
+    if (e < E && lane < slices) t = g_sum[int64_t(lane) * E + e];
+    t = wave_reduce_dd(t);
+    if (e < E && lane == 0) out_grad[e] = sgn * (t.hi + t.lo);
     if (blockIdx.x == 0) {
         for (int q = 0; q < W; ++q) {
             dd pacc = dd{0.0, 0.0};
-            for (int64_t v = threadIdx.x; v < waves; v += kBlock)
+            for (int64_t v = threadIdx.x; v < items; v += kBlock)
                 pacc = dd_add(pacc, perm_part[v * 2 + q]);
             const dd pt = block_reduce_dd(pacc, red);
             if (threadIdx.x == 0) out_perm[q] = 2.0 * sgn * (pt.hi + pt.lo);
@@ -143,8 +173,9 @@ __global__ __launch_bounds__(kBlock) void finalize_perm_only(const dd *__restric
 }
 
 template <int N, bool CPLX>
-static void launch_grad_n(const GradPlan &p, const double *acol, const double *x0, dd *pp, dd *gp, bool want_grad, double *out_perm,
-                          double *out_grad, hipStream_t stream)
+static void launch_grad_n(const GradPlan &p, const double *acol, const double *x0, dd *pp, dd *gp,
+                          dd *gs, bool want_grad, double *out_perm, double *out_grad,
+                          hipStream_t stream)
 {
     if constexpr (N <= 24)
         hipLaunchKernelGGL((sweep_grad<N, CPLX>), dim3(unsigned(p.waves)), dim3(kGradBlock), 0,
@@ -154,16 +185,22 @@ static void launch_grad_n(const GradPlan &p, const double *acol, const double *x
         hipLaunchKernelGGL((sweep_grad_large<N, CPLX>), dim3(unsigned(p.waves)), dim3(kGradBlock),
                            0, stream, acol, x0, pp, gp, p.log2_chunk, p.log2_reseed,
                            p.lanes_active, int(want_grad));
-    if (want_grad)
-        hipLaunchKernelGGL((finalize_grad<N, CPLX>), dim3(unsigned(N * N * (CPLX ? 2 : 1))),
-                           dim3(kBlock), 0, stream, pp, gp, p.waves, out_perm, out_grad);
-    else
+    if (want_grad) {
+        constexpr int E = N * N * (CPLX ? 2 : 1);
+        const int slices = grad_sum_slices(p.waves);
+        hipLaunchKernelGGL((grad_slice_sums<N, CPLX>),
+                           dim3(unsigned((E + kWave - 1) / kWave), unsigned(slices)), dim3(kBlock),
+                           0, stream, gp, p.waves, slices, gs);
+        hipLaunchKernelGGL((finalize_grad<N, CPLX>),
+                           dim3(unsigned((E + kWavesPerBlock - 1) / kWavesPerBlock)), dim3(kBlock),
+                           0, stream, pp, gs, p.waves, slices, out_perm, out_grad);
+    } else
         hipLaunchKernelGGL(finalize_perm_only<CPLX>, dim3(1), dim3(kBlock), 0, stream, pp, p.waves,
                            (N & 1) ? 2.0 : -2.0, out_perm);
 }
 
-using GradLauncher = void (*)(const GradPlan &, const double *, const double *, dd *, dd *, bool,
-                              double *, double *, hipStream_t);
+using GradLauncher = void (*)(const GradPlan &, const double *, const double *, dd *, dd *, dd *,
+                              bool, double *, double *, hipStream_t);
 
 template <bool CPLX, int... Ns>
 struct GradTable {
@@ -242,10 +279,11 @@ int launch_grad_or_small(int n, bool cplx, const void *A, int64_t lda, void *out
     double *x0 = reinterpret_cast<double *>(ws + L.x0);
     dd *pp = reinterpret_cast<dd *>(ws + L.perm_partials);
     dd *gp = reinterpret_cast<dd *>(ws + L.grad_partials);
+    dd *gs = reinterpret_cast<dd *>(ws + L.grad_sums);
     launch_stage(n, cplx, A, lda, acol, x0, stream);
     GradLauncher f = cplx ? GradC128Table::get(n) : GradF64Table::get(n);
     if (!f) return PERM_EUNSUPPORTED;
-    f(p, acol, x0, pp, gp, want_grad, static_cast<double *>(out_perm),
+    f(p, acol, x0, pp, gp, gs, want_grad, static_cast<double *>(out_perm),
       static_cast<double *>(out_grad), stream);
     return hipGetLastError() == hipSuccess ? PERM_OK : PERM_EHIP;
 }
